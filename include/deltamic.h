@@ -1,0 +1,209 @@
+/*
+ * deltamic.h -- C ABI of the MI355X (gfx950) mesh-transform microscope renderer.
+ *
+ * The library renders a synthetic 3D fluorescence image from a closed
+ * triangle mesh and a Gaussian point-spread function, and returns the
+ * gradient of a scalar loss with respect to the vertex positions and the PSF
+ * covariance.  It follows the image-formation model of the paper (Sec. 3):
+ * the image is the convolution of a fluorophore density with the PSF
+ * (Eq. 1), computed as a product in Fourier space; the density's transform is
+ * the closed-form transform of the triangle mesh (Sec. 4, Eq. 5-12); the
+ * PSF is the Gaussian of Eq. 2 with covariance Sigma; the mesh transform is
+ * evaluated only on the narrow band of frequencies where the PSF transform
+ * exceeds a threshold (Sec. 5.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Units     vertex positions, grid spacing, grid origin and the PSF
+ *            covariance use one length unit (Sigma in length^2).
+ *  Grid      n[0] x n[1] x n[2] voxels (x, y, z), voxel (i,j,k) centred at
+ *            origin + (i, j, k) * spacing; images are float32 arrays laid out
+ *            [n0][n1][n2], z fastest.  The image is periodic over the box
+ *            L = n * spacing (it is produced by an inverse DFT).
+ *  Spectrum  frequencies xi = 2 pi k / L with k the integer DFT frequencies
+ *            (fftfreq order); the image is Re(ifftn(h_hat * u_hat * band)) /
+ *            (spacing_x spacing_y spacing_z).  On even axes the Nyquist
+ *            coefficient of that real part is the average of the two aliases
+ *            +-N/2; the library evaluates both.
+ *  Band      a frequency is evaluated iff xi^T Sigma xi < -2 ln(band_tau)
+ *            (equivalently h_hat(xi) > band_tau), decided in float64 with the
+ *            order ((((Sxx x x + Syy y y) + Szz z z) + 2 Sxy x y) + 2 Sxz x z)
+ *            + 2 Syz y z and xi_j = (2 pi k_j) / (n_j spacing_j).
+ *            band_tau = 0 evaluates the full spectrum; band_tau >= 1 gives an
+ *            empty band and a zero image.
+ *  Density   DM_VOLUME:  indicator function of the region the closed mesh
+ *            encloses (the paper's suggested volumetric extension, Sec. 3.3
+ *            and Sec. 7); its transform at xi = 0 is the enclosed volume.
+ *            DM_SURFACE: fluorophores on the surface, normalised by the total
+ *            area so that the image integrates to one (Eq. 3-5).
+ *  Memory    pointers named *_dev are device (HBM) pointers on the handle's
+ *            device, owned by the caller and never freed by the library.
+ *            Host structs are read during the call only.
+ *  Streams   `stream` is a hipStream_t (NULL = default stream).  Calls
+ *            enqueue their work on it and return; outputs are valid once the
+ *            stream has been synchronised.  A handle is not thread-safe:
+ *            serialise calls on one handle.
+ *  Errors    every entry point returns a dm_status; on failure nothing has
+ *            been written to any output and dm_last_error() describes the
+ *            cause.  Input checks happen on the host before any work is
+ *            enqueued.
+ *  Results   deterministic: the same inputs give bitwise identical outputs
+ *            (all reductions run in a fixed order; no floating-point
+ *            atomics).
+ */
+#ifndef DELTAMIC_H
+#define DELTAMIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DM_OK = 0,
+  DM_ERR_ARG = -1,      /* null pointer, bad size or option */
+  DM_ERR_MESH = -2,     /* face index out of range, open mesh in VOLUME mode */
+  DM_ERR_PSF = -3,      /* covariance not symmetric positive definite */
+  DM_ERR_BUDGET = -4,   /* the call's device memory would exceed the handle budget */
+  DM_ERR_DEVICE = -5,   /* a HIP runtime call failed */
+  DM_ERR_FFT = -6,      /* a rocFFT call failed */
+  DM_ERR_BUSY = -7,     /* serving queue full */
+  DM_ERR_STATE = -8     /* object used in the wrong state (e.g. unknown ticket) */
+} dm_status;
+
+typedef enum {
+  DM_VOLUME = 0,        /* indicator density of the enclosed region */
+  DM_SURFACE = 1        /* area-normalised surface density (Eq. 3-5) */
+} dm_mode;
+
+typedef struct dm_handle dm_handle;
+typedef struct dm_topology dm_topology;
+
+typedef struct {
+  int32_t n[3];         /* voxels along x, y, z (each >= 1) */
+  float spacing[3];     /* voxel size along x, y, z (> 0) */
+  float origin[3];      /* position of voxel (0,0,0) */
+  float band_tau;       /* band threshold on the PSF transform, in [0, inf) */
+  int32_t mode;         /* dm_mode */
+} dm_grid;
+
+typedef struct {
+  float sigma[6];       /* covariance xx, yy, zz, xy, xz, yz (length^2) */
+} dm_psf;
+
+typedef struct {
+  const float* verts_dev;     /* [n_verts][3] positions */
+  int32_t n_verts;
+  const dm_topology* topo;    /* faces, validated at dm_topology_create */
+} dm_mesh;
+
+/* ---------------------------------------------------------------- handle */
+
+/* Create a handle bound to HIP device `device`.  `hbm_budget_bytes` caps the
+ * device memory the handle's workspaces and caches may hold (0 = no cap).
+ * Returns DM_ERR_DEVICE if the device is absent or not gfx950. */
+dm_status dm_create(dm_handle** out, int device, size_t hbm_budget_bytes);
+
+/* Free the handle, its caches, FFT plans and workspaces.  Synchronises the
+ * device first.  NULL is accepted. */
+dm_status dm_destroy(dm_handle* h);
+
+/* Bytes of device memory the handle currently holds. */
+dm_status dm_memory_in_use(const dm_handle* h, size_t* bytes);
+
+/* ------------------------------------------------------------- topology */
+
+/* Validate the faces of a triangle mesh and build its vertex-incidence
+ * table (the one-ring of each vertex, the triangles "v star" of Eq. 6).
+ * faces: [n_faces][3] int32 vertex indices, counter-clockwise seen from
+ * outside; a host pointer if faces_on_device == 0, else a device pointer.
+ * Fails with DM_ERR_MESH if an index is outside [0, n_verts).  Records
+ * whether the mesh is closed and consistently oriented (every directed edge
+ * matched by its reverse exactly once), which DM_VOLUME requires.  The
+ * topology keeps its own device copy of the faces.  Synchronous. */
+dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces, int32_t n_verts,
+                             int faces_on_device, dm_topology** out);
+dm_status dm_topology_destroy(dm_topology* t);
+/* closed = 1 if closed and consistently oriented. */
+dm_status dm_topology_info(const dm_topology* t, int32_t* n_faces, int32_t* n_verts, int32_t* closed);
+
+/* ------------------------------------------------------------------ band */
+
+/* Number of frequency entries evaluated for (grid, psf): the in-band
+ * positions of the half spectrum [n0][n1][n2/2+1], counting both aliases of
+ * Nyquist positions.  Builds and caches the band on the device if needed
+ * (synchronises `stream` on a cache miss). */
+dm_status dm_band_size(dm_handle* h, const dm_grid* g, const dm_psf* psf, int64_t* n_entries, void* stream);
+
+/* Copy the band to host memory, in the library's evaluation order:
+ * k_out [n][3] integer frequencies, pos_out [n] linear half-spectrum
+ * position (i0*n1 + i1)*(n2/2+1) + i2, weight_out [n] the alias weight
+ * (1/2 for entries at Nyquist positions, else 1).  Any output may be NULL.
+ * Synchronous. */
+dm_status dm_band_export(dm_handle* h, const dm_grid* g, const dm_psf* psf, int32_t* k_out,
+                         int64_t* pos_out, float* weight_out, void* stream);
+
+/* ---------------------------------------------------------------- render */
+
+/* Forward render (Sec. 3-4): image_dev [n0][n1][n2] float32 receives the
+ * image.  If spectrum_dev is not NULL it receives the mesh transform u_hat
+ * at every band entry (complex64 as float pairs, [n_entries][2], band order),
+ * which dm_render_vjp can reuse.  DM_VOLUME requires a closed topology.
+ * Either output may be NULL (both NULL is an argument error). */
+dm_status dm_render(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, const dm_grid* g,
+                    float* image_dev, float* spectrum_dev, void* stream);
+
+/* Gradient of a scalar loss L(image) (the paper's backward pass, Eq. 6-10,
+ * and the PSF gradient of Sec. 5.2) given dL_dimage_dev [n0][n1][n2]:
+ *   dL_dverts_dev [n_verts][3]  (may be NULL)
+ *   dL_dsigma_dev [6] with respect to (xx, yy, zz, xy, xz, yz); an
+ *                 off-diagonal entry stands for both symmetric positions
+ *                 of Sigma (may be NULL)
+ *   image_dev     optional: the forward image, computed in the same call
+ * The band is held fixed (it depends on Sigma only through the threshold).
+ * spectrum_in_dev, if not NULL, is the spectrum dm_render returned for the
+ * same mesh, psf and grid, and saves the forward sweep when image_dev is
+ * NULL.  Without it the forward sweep runs when image_dev or dL_dsigma_dev
+ * is requested. */
+dm_status dm_render_vjp(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, const dm_grid* g,
+                        const float* dL_dimage_dev, float* dL_dverts_dev, float* dL_dsigma_dev,
+                        float* image_dev, const float* spectrum_in_dev, void* stream);
+
+/* Mesh transform at arbitrary integer frequencies: out_dev [n][2] receives
+ * u_hat(2 pi k / L) for k_dev [n][3] (int32, device), with the grid's
+ * origin as phase origin and the grid's mode (DM_SURFACE normalised by the
+ * area).  No band, no PSF. */
+dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev,
+                            int64_t n, float* out_dev, void* stream);
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* Kernel timing: while enabled, the handle records HIP events on the call's
+ * stream around every launch of the two mesh-transform sweeps (the forward
+ * sweep of Eq. 5/7-8 and the gradient sweep of Eq. 6/9-10).  dm_timing_read
+ * waits for those events and returns, per sweep kind, the number of launches,
+ * the summed duration in milliseconds and the summed frequency-triangle
+ * pairs they evaluated; reset != 0 clears the counters.  Any output may be
+ * NULL. */
+typedef struct {
+  int64_t launches;
+  double ms;
+  double pairs;
+} dm_kernel_time;
+
+dm_status dm_timing_enable(dm_handle* h, int enable);
+dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time* vjp_sweep, int reset);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* dm_last_error(void);
+
+/* Library version string. */
+const char* dm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DELTAMIC_H */

@@ -227,19 +227,24 @@ def mesh_transform(V, F, xi, grid, mode: int) -> np.ndarray:
     return u
 
 
-def spectrum(V, F, grid, sigma6, mode: int | None = None):
-    """Full-grid spectrum I_hat = h u on the band (zero elsewhere)."""
+def spectrum(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None):
+    """Full-grid spectrum I_hat = h u on the band (zero elsewhere).
+
+    ``band_sigma6`` (default: ``sigma6``) selects the covariance that decides
+    the band, so that derivative checks can hold the band fixed."""
     mode = grid.mode if mode is None else mode
     xi, h, band = otf_and_band(grid, sigma6)
+    if band_sigma6 is not None:
+        band = otf_and_band(grid, band_sigma6)[2]
     u = np.zeros(grid.n, dtype=np.complex128)
     if band.any():
         u[band] = mesh_transform(V, F, xi[band], grid, mode)
     return h * u * band, (xi, h, band, u)
 
 
-def render(V, F, grid, sigma6, mode: int | None = None) -> np.ndarray:
+def render(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None) -> np.ndarray:
     """Image on the grid: Re(ifftn(I_hat)) / (Dx Dy Dz)."""
-    Ihat, _ = spectrum(V, F, grid, sigma6, mode)
+    Ihat, _ = spectrum(V, F, grid, sigma6, mode, band_sigma6)
     dvol = float(grid.spacing[0]) * float(grid.spacing[1]) * float(grid.spacing[2])
     return np.real(np.fft.ifftn(Ihat)) / dvol
 

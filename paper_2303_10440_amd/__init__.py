@@ -1,0 +1,381 @@
+"""Python binding of libdeltamic (the gfx950 mesh-transform microscope renderer).
+
+Argument marshalling only: every step of the render and of its gradient runs
+in the HIP kernels behind the C ABI of ``include/deltamic.h``.  PyTorch is
+used for device memory and streams.  There is no CPU fallback: if the
+library is missing or no gfx950 device is present, calls raise.
+
+Typical use::
+
+    import paper_2303_10440_amd as dm
+    h = dm.Handle(device=0)
+    topo = h.topology(faces)                     # int32 [n_t, 3], validated once
+    img = dm.render(h, verts, topo, sigma6, grid)  # verts: float32 cuda [n_v, 3]
+
+    # differentiable:
+    img = dm.RenderFunction.apply(verts, sigma6_tensor, h, topo, grid)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import pathlib
+import re
+
+import numpy as np
+
+HERE = pathlib.Path(__file__).resolve().parent
+LIB_PATH = HERE / "libdeltamic.so"
+HEADER = HERE.parent / "include" / "deltamic.h"
+
+VOLUME, SURFACE = 0, 1
+STATUS = {0: "DM_OK", -1: "DM_ERR_ARG", -2: "DM_ERR_MESH", -3: "DM_ERR_PSF", -4: "DM_ERR_BUDGET",
+          -5: "DM_ERR_DEVICE", -6: "DM_ERR_FFT", -7: "DM_ERR_BUSY", -8: "DM_ERR_STATE"}
+
+
+class DeltamicError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func} failed with {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("spacing", ctypes.c_float * 3), ("origin", ctypes.c_float * 3),
+                ("band_tau", ctypes.c_float), ("mode", ctypes.c_int32)]
+
+
+class CPsf(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_float * 6)]
+
+
+class CKernelTime(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("pairs", ctypes.c_double)]
+
+
+class CMesh(ctypes.Structure):
+    _fields_ = [("verts_dev", ctypes.c_void_p), ("n_verts", ctypes.c_int32), ("topo", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2303_10440_amd/csrc/build.sh "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(str(LIB_PATH))
+    vp, i32, i64, fp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)
+    sig = {
+        "dm_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t],
+        "dm_destroy": [vp],
+        "dm_memory_in_use": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "dm_topology_create": [vp, vp, i32, i32, ctypes.c_int, ctypes.POINTER(vp)],
+        "dm_topology_destroy": [vp],
+        "dm_topology_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "dm_band_size": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), ctypes.POINTER(i64), vp],
+        "dm_band_export": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), vp, vp, vp, vp],
+        "dm_render": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CPsf), ctypes.POINTER(CGrid), vp, vp, vp],
+        "dm_render_vjp": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CPsf), ctypes.POINTER(CGrid), vp, vp, vp, vp,
+                          vp, vp],
+        "dm_mesh_transform": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CGrid), vp, i64, vp, vp],
+        "dm_timing_enable": [vp, ctypes.c_int],
+        "dm_timing_read": [vp, ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime), ctypes.c_int],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.dm_last_error.restype = ctypes.c_char_p
+    L.dm_last_error.argtypes = []
+    L.dm_version.restype = ctypes.c_char_p
+    L.dm_version.argtypes = []
+    _lib = L
+    return L
+
+
+def lib():
+    return _load()
+
+
+def header_symbols() -> list[str]:
+    """Entry points declared in include/deltamic.h."""
+    text = HEADER.read_text()
+    return sorted(set(re.findall(r"^\s*(?:dm_status|const char\*)\s+(dm_\w+)\s*\(", text, flags=re.M)))
+
+
+def _check(status: int, func: str):
+    if status != 0:
+        raise DeltamicError(status, func, _load().dm_last_error().decode())
+
+
+def version() -> str:
+    return _load().dm_version().decode()
+
+
+# ------------------------------------------------------------------ helpers
+def _grid(g) -> CGrid:
+    c = CGrid()
+    for j in range(3):
+        c.n[j] = int(g.n[j])
+        c.spacing[j] = float(g.spacing[j])
+        c.origin[j] = float(g.origin[j])
+    c.band_tau = float(g.tau)
+    c.mode = int(g.mode)
+    return c
+
+
+def _psf(sigma6) -> CPsf:
+    p = CPsf()
+    vals = sigma6.detach().cpu().tolist() if hasattr(sigma6, "detach") else list(sigma6)
+    if len(vals) != 6:
+        raise ValueError("sigma must have 6 entries (xx, yy, zz, xy, xz, yz)")
+    for j in range(6):
+        p.sigma[j] = float(vals[j])
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device: int):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_tensor(x, dtype, shape_last=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if shape_last is not None and (x.dim() != 2 or x.shape[1] != shape_last):
+        raise ValueError(f"{name} must have shape [n, {shape_last}]")
+    return x.contiguous()
+
+
+class Handle:
+    """Owns a dm_handle on one device (workspace, band cache, FFT plans)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        L = _load()
+        self.device = int(device)
+        self._h = ctypes.c_void_p()
+        _check(L.dm_create(ctypes.byref(self._h), self.device, ctypes.c_size_t(int(hbm_budget_bytes))), "dm_create")
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _load().dm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def memory_in_use(self) -> int:
+        v = ctypes.c_size_t()
+        _check(_load().dm_memory_in_use(self._h, ctypes.byref(v)), "dm_memory_in_use")
+        return int(v.value)
+
+    def timing(self, enable: bool):
+        _check(_load().dm_timing_enable(self._h, 1 if enable else 0), "dm_timing_enable")
+
+    def timing_read(self, reset: bool = True) -> dict:
+        """{'fwd': (launches, ms, pairs), 'vjp': (...)} from the HIP events the
+        library records around each sweep launch."""
+        a, b = CKernelTime(), CKernelTime()
+        _check(_load().dm_timing_read(self._h, ctypes.byref(a), ctypes.byref(b), 1 if reset else 0),
+               "dm_timing_read")
+        return {"fwd": (int(a.launches), float(a.ms), float(a.pairs)),
+                "vjp": (int(b.launches), float(b.ms), float(b.pairs))}
+
+    def topology(self, faces, n_verts: int | None = None) -> "Topology":
+        return Topology(self, faces, n_verts)
+
+
+class Topology:
+    """Validated faces + vertex incidence of one mesh (dm_topology)."""
+
+    def __init__(self, handle: Handle, faces, n_verts: int | None = None):
+        L = _load()
+        self.handle = handle
+        torch = _torch()
+        if isinstance(faces, torch.Tensor):
+            f = faces.detach().to(torch.int32).contiguous()
+            on_dev = 1 if f.is_cuda else 0
+            arr = f
+            ptr = f.data_ptr()
+            nf = f.shape[0]
+            nv = int(n_verts) if n_verts is not None else (int(f.max().item()) + 1 if nf else 0)
+        else:
+            arr = np.ascontiguousarray(np.asarray(faces, dtype=np.int32))
+            on_dev = 0
+            ptr = arr.ctypes.data
+            nf = arr.shape[0]
+            nv = int(n_verts) if n_verts is not None else (int(arr.max()) + 1 if nf else 0)
+        if arr.ndim != 2 or arr.shape[1] != 3:
+            raise ValueError("faces must have shape [n_t, 3]")
+        self._t = ctypes.c_void_p()
+        _check(L.dm_topology_create(handle.ptr, ctypes.c_void_p(ptr), int(nf), int(nv), on_dev, ctypes.byref(self._t)),
+               "dm_topology_create")
+        self.n_faces, self.n_verts = int(nf), int(nv)
+        c = ctypes.c_int32()
+        _check(L.dm_topology_info(self._t, None, None, ctypes.byref(c)), "dm_topology_info")
+        self.closed = bool(c.value)
+
+    @property
+    def ptr(self):
+        return self._t
+
+    def close(self):
+        if getattr(self, "_t", None) and self._t.value:
+            _load().dm_topology_destroy(self._t)
+            self._t = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _mesh(verts, topo: Topology) -> CMesh:
+    m = CMesh()
+    m.verts_dev = ctypes.c_void_p(verts.data_ptr())
+    m.n_verts = int(verts.shape[0])
+    m.topo = topo.ptr
+    return m
+
+
+# ----------------------------------------------------------------- calls
+def band_size(h: Handle, grid, sigma6) -> int:
+    n = ctypes.c_int64()
+    g, p = _grid(grid), _psf(sigma6)
+    _check(_load().dm_band_size(h.ptr, ctypes.byref(g), ctypes.byref(p), ctypes.byref(n), _stream(h.device)),
+           "dm_band_size")
+    return int(n.value)
+
+
+def band_export(h: Handle, grid, sigma6) -> dict:
+    n = band_size(h, grid, sigma6)
+    k = np.zeros((n, 3), np.int32)
+    pos = np.zeros(n, np.int64)
+    w = np.zeros(n, np.float32)
+    g, p = _grid(grid), _psf(sigma6)
+    _check(_load().dm_band_export(h.ptr, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(k.ctypes.data),
+                                  ctypes.c_void_p(pos.ctypes.data), ctypes.c_void_p(w.ctypes.data),
+                                  _stream(h.device)), "dm_band_export")
+    return {"k": k, "pos": pos, "weight": w}
+
+
+def render(h: Handle, verts, topo: Topology, sigma6, grid, spectrum: bool = False):
+    """Image [n0, n1, n2] float32 (and the band spectrum [n_entries, 2] if asked)."""
+    torch = _torch()
+    verts = _dev_tensor(verts, torch.float32, 3, "verts")
+    g, p, m = _grid(grid), _psf(sigma6), _mesh(verts, topo)
+    img = torch.empty(tuple(int(x) for x in grid.n), dtype=torch.float32, device=verts.device)
+    spec = None
+    if spectrum:
+        spec = torch.empty((band_size(h, grid, sigma6), 2), dtype=torch.float32, device=verts.device)
+    _check(_load().dm_render(h.ptr, ctypes.byref(m), ctypes.byref(p), ctypes.byref(g), ctypes.c_void_p(img.data_ptr()),
+                             ctypes.c_void_p(spec.data_ptr() if spec is not None else 0), _stream(h.device)),
+           "dm_render")
+    return (img, spec) if spectrum else img
+
+
+def render_vjp(h: Handle, verts, topo: Topology, sigma6, grid, dL_dimage, want_verts: bool = True,
+               want_sigma: bool = True, want_image: bool = False, spectrum_in=None):
+    """(dL/dverts [n_v,3] | None, dL/dsigma [6] | None, image | None)."""
+    torch = _torch()
+    verts = _dev_tensor(verts, torch.float32, 3, "verts")
+    gI = _dev_tensor(dL_dimage, torch.float32, None, "dL_dimage")
+    if tuple(gI.shape) != tuple(int(x) for x in grid.n):
+        raise ValueError("dL_dimage must have the grid's shape")
+    g, p, m = _grid(grid), _psf(sigma6), _mesh(verts, topo)
+    dv = torch.empty_like(verts) if want_verts else None
+    ds = torch.empty(6, dtype=torch.float32, device=verts.device) if want_sigma else None
+    img = torch.empty(tuple(int(x) for x in grid.n), dtype=torch.float32, device=verts.device) if want_image else None
+    sp = None
+    if spectrum_in is not None:
+        sp = _dev_tensor(spectrum_in, torch.float32, 2, "spectrum_in")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+    _check(_load().dm_render_vjp(h.ptr, ctypes.byref(m), ctypes.byref(p), ctypes.byref(g), ptr(gI), ptr(dv), ptr(ds),
+                                 ptr(img), ptr(sp), _stream(h.device)), "dm_render_vjp")
+    return dv, ds, img
+
+
+def mesh_transform(h: Handle, verts, topo: Topology, grid, k):
+    """u_hat(2 pi k / L) as complex64 [n] for integer frequencies k [n, 3]."""
+    torch = _torch()
+    verts = _dev_tensor(verts, torch.float32, 3, "verts")
+    if not isinstance(k, torch.Tensor):
+        k = torch.as_tensor(np.asarray(k, dtype=np.int32))
+    k = k.to(device=verts.device, dtype=torch.int32).contiguous()
+    out = torch.empty((k.shape[0], 2), dtype=torch.float32, device=verts.device)
+    g, m = _grid(grid), _mesh(verts, topo)
+    _check(_load().dm_mesh_transform(h.ptr, ctypes.byref(m), ctypes.byref(g), ctypes.c_void_p(k.data_ptr()),
+                                     int(k.shape[0]), ctypes.c_void_p(out.data_ptr()), _stream(h.device)),
+           "dm_mesh_transform")
+    return torch.view_as_complex(out)
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class RenderFunction(torch.autograd.Function):
+        """image = render(verts, sigma6); backward gives dL/dverts and dL/dsigma6.
+
+        sigma6 is a 6-vector tensor (xx, yy, zz, xy, xz, yz); its values are
+        read on the host (the band depends on them).  The forward saves the
+        band spectrum so the backward skips the forward sweep."""
+
+        @staticmethod
+        def forward(ctx, verts, sigma6, handle, topo, grid):
+            img, spec = render(handle, verts, topo, sigma6, grid, spectrum=True)
+            ctx.save_for_backward(verts, sigma6, spec)
+            ctx.handle, ctx.topo, ctx.grid = handle, topo, grid
+            return img
+
+        @staticmethod
+        def backward(ctx, grad):
+            verts, sigma6, spec = ctx.saved_tensors
+            dv, ds, _ = render_vjp(ctx.handle, verts, ctx.topo, sigma6, ctx.grid, grad.contiguous(),
+                                   want_verts=ctx.needs_input_grad[0], want_sigma=ctx.needs_input_grad[1],
+                                   spectrum_in=spec)
+            if ds is not None:
+                ds = ds.to(sigma6.dtype).to(sigma6.device)
+            return dv, ds, None, None, None
+
+    return RenderFunction
+
+
+class _Lazy:
+    _cls = None
+
+    def __get__(self, obj, owner):
+        if _Lazy._cls is None:
+            _Lazy._cls = _autograd_function()
+        return _Lazy._cls
+
+
+class _NS:
+    RenderFunction = _Lazy()
+
+
+def __getattr__(name):
+    if name == "RenderFunction":
+        return _NS.RenderFunction
+    raise AttributeError(name)
+
+
+_load()

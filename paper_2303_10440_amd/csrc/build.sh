@@ -1,0 +1,16 @@
+#!/bin/bash
+# Builds libdeltamic.so for gfx950 in this directory's parent package folder.
+set -euo pipefail
+HERE="$(cd "$(dirname "${BASH_SOURCE[0]}")" && pwd)"
+OUT="${1:-$HERE/../libdeltamic.so}"
+ROCM="${ROCM_PATH:-/opt/rocm}"
+FLAGS=(-O3 -std=c++17 -fPIC --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops
+       -I"$HERE/../../include" -I"$ROCM/include")
+TMP="$(mktemp -d)"
+trap 'rm -rf "$TMP"' EXIT
+"$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_kernels.hip" -o "$TMP/dm_kernels.o"
+"$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_host.cpp" -o "$TMP/dm_host.o"
+"$ROCM/bin/hipcc" -shared --offload-arch=gfx950 -o "$OUT.tmp" "$TMP/dm_kernels.o" "$TMP/dm_host.o" \
+  -L"$ROCM/lib" -lrocfft -Wl,-rpath,"$ROCM/lib"
+mv -f "$OUT.tmp" "$OUT"
+echo "built $OUT"

@@ -1,0 +1,89 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dm {
+
+// Per-call mesh quantities computed on the device by the mesh-prep kernels.
+struct MeshInfo {
+  float c[3];        // reference point for phases: vertex centroid
+  float pad0;
+  double cu[3];      // (c - origin) / L, revolutions per unit integer frequency
+  double area;       // |Lambda| = sum_T A_T
+  double volume;     // enclosed volume (signed cones from c)
+};
+
+// Grid constants passed by value to kernels.
+struct GridC {
+  int n0, n1, n2, n2h;     // voxel counts, n2h = n2/2 + 1
+  double L[3];             // box lengths n_j * spacing_j
+  double origin[3];
+  float Linv[3];           // 1 / L_j (float)
+  float two_pi_over_L[3];  // 2 pi / L_j (float)
+  float inv_LV;            // 1 / (Lx Ly Lz)
+};
+
+// Band description on the device (see band.hip).
+struct BandDev {
+  int64_t n_entries;
+  int64_t n_pos;           // n0 * n1 * n2h
+  float4* kf;              // [n_entries] {kx, ky, kz, h_hat}
+  float* wgt;              // [n_entries] alias weight (1 or 1/2)
+  int32_t* pos;            // [n_entries] half-spectrum position
+  int32_t* map;            // [n_pos] first entry | (count-1) << 30, or -1
+};
+
+// Triangle record for the sweeps: 16 floats (one 64-byte scalar load).
+//  [0..2] u1_hi, [3..5] u1_lo : (v1 - c)/L split into a 12-bit grid part and rest
+//  [6..8] e2 = (v2 - v1)/L,  [9..11] e3 = (v3 - v1)/L
+//  [12..14] VOLUME: n_T / L (n_T = (v2-v1)x(v3-v1));  SURFACE: [12] = 2 A_T
+//  [15] unused
+constexpr int TRI_REC = 16;
+constexpr float PHASE_GRID = 4096.0f;   // 2^12
+
+// Band-entry record for the VJP sweep: 8 floats (one 32-byte scalar load).
+//  {kx, ky, kz, Wr}, {Wi, xi_x, xi_y, xi_z}
+
+// ---- launchers (defined in dm_kernels.hip); all enqueue on `s` ----
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+hipError_t launch_band_count(const GridC& g, const double* sigma6, double qmax, int32_t* cnt, int64_t n_slots,
+                             hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* block_tmp, int64_t* total,
+                       hipStream_t s);
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_band_fill(const GridC& g, const double* sigma6, double qmax, const int32_t* cnt,
+                            const int32_t* off, int64_t n_slots, BandDev b, hipStream_t s);
+
+hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces, int nt,
+                            float* tri_rec, MeshInfo* info, double* block_tmp, int tmp_blocks, hipStream_t s);
+int mesh_prep_blocks(int nt);
+
+hipError_t launch_fwd_sweep(int mode, const float4* kf, int64_t nE, const float* tri_rec, int nt,
+                            int tris_per_chunk, int n_chunks, float2* part, hipStream_t s);
+hipError_t launch_fwd_finalize(int mode, const GridC& g, BandDev b, const float2* part, int n_chunks,
+                               const MeshInfo* info, float2* spec_out, float2* xhalf, hipStream_t s);
+hipError_t launch_spec_scatter(const GridC& g, BandDev b, const float2* spec, float2* xhalf, hipStream_t s);
+
+hipError_t launch_adjoint(int mode, const GridC& g, BandDev b, const float2* ghat, const MeshInfo* info,
+                          const float2* spec, float4* erec, double* dsig_part, int dsig_blocks, hipStream_t s);
+int adjoint_blocks(const GridC& g);
+hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hipStream_t s);
+
+hipError_t launch_vjp_sweep(int mode, const float* tri_rec, int nt, const float4* erec, int64_t nE,
+                            int ents_per_chunk, int n_chunks, float* part, hipStream_t s);
+hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* red, hipStream_t s);
+hipError_t launch_surface_scalar(const float* red, const float* tri_rec, int nt, const MeshInfo* info,
+                                 double* out_R, hipStream_t s);
+hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, int nt,
+                                const int32_t* csr_off, const int32_t* csr_ent, const float* red,
+                                const double* R, float* dV, hipStream_t s);
+
+hipError_t launch_points_prepare(const GridC& g, const int32_t* k, int64_t n, float4* kf, hipStream_t s);
+hipError_t launch_points_finalize(int mode, const GridC& g, const float4* kf, int64_t n, const float2* part,
+                                  int n_chunks, const MeshInfo* info, float2* out, hipStream_t s);
+
+inline int nchannels(int mode) { return mode == 0 ? 3 : 10; }
+
+}  // namespace dm

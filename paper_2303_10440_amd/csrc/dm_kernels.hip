@@ -1,0 +1,939 @@
+// gfx950 kernels of the mesh-transform renderer.
+//
+// Method (paper Sec. 4): the transform of a triangle T at frequency xi is
+// 2 A_T f_T(xi) with f_T the second divided difference of exp at the nodes
+// z_p = -i v_p.xi (Eq. 7-8); its vertex derivatives are third divided
+// differences with a repeated node (Eq. 9-10).  Near-coincident phases
+// (Sec. 4.1.3) are handled here by two evaluation schemes that are exact in
+// real arithmetic and stable in float32:
+//   * nodes spread by less than one radian: a series about the node mean,
+//     written in the elementary symmetric polynomials E2, E3 of the centred
+//     phases (complete homogeneous polynomials h_n of the nodes divided by
+//     (n+2)!);
+//   * otherwise: the nodes are sorted, DD3 = [DD2(mid,hi) - DD2(lo,mid)] /
+//     (z_hi - z_lo) with each DD2 in its sinc form, and the repeated-node
+//     DD4 from the same recurrence with the second phi-function
+//     phi2(z) = (e^z - 1 - z)/z^2.
+// Phases are carried in revolutions (k . u with integer k and u = x / L), so
+// the large part of every phase is reduced exactly before the hardware
+// sine and cosine (v_sin_f32 / v_cos_f32 take revolutions).
+//
+// Work layout: the forward sweep puts one band frequency on each lane and
+// streams triangles as wave-uniform records through the scalar data cache;
+// the VJP sweep puts one triangle on each lane and streams frequencies the
+// same way.  Every reduction is a fixed-order sum (no atomics), so results
+// are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dm_internal.h"
+
+namespace dm {
+
+namespace {
+
+constexpr float TWO_PI_F = 6.283185307179586477f;
+constexpr float PI_F = 3.141592653589793238f;
+constexpr double TWO_PI_D = 6.283185307179586476925286766559;
+// Series branch when the node spread is below one radian.
+constexpr float SERIES_REV = 0.15915494309189535f;   // 1 / (2 pi)
+
+__device__ __forceinline__ float reduce_rev(float r) { return r - __builtin_rintf(r); }
+
+// e^{-2 pi i r} for r in revolutions, r already in [-1/2, 1/2].
+__device__ __forceinline__ void cis_neg(float r, float& c, float& s_neg) {
+  c = __builtin_amdgcn_cosf(r);
+  s_neg = -__builtin_amdgcn_sinf(r);
+}
+
+// sin(x)/x for x >= 0 given sin(x): polynomial below 0.5, quotient above.
+__device__ __forceinline__ float sinc_from(float x, float sinx, float inv_x) {
+  const float x2 = x * x;
+  const float p = fmaf(x2, fmaf(x2, fmaf(x2, -1.9841269841e-4f, 8.3333333333e-3f), -0.16666666667f), 1.0f);
+  return x < 0.5f ? p : sinx * inv_x;
+}
+
+// Integer-frequency phase of vertex 1 plus the two relative phases (revolutions).
+__device__ __forceinline__ void tri_phases(float kx, float ky, float kz, const float* r, float& t1, float& d2,
+                                           float& d3) {
+  float th = fmaf(kz, r[2], fmaf(ky, r[1], kx * r[0]));   // exact: 12-bit grid part
+  th -= __builtin_rintf(th);
+  t1 = th + fmaf(kz, r[5], fmaf(ky, r[4], kx * r[3]));
+  d2 = fmaf(kz, r[8], fmaf(ky, r[7], kx * r[6]));
+  d3 = fmaf(kz, r[11], fmaf(ky, r[10], kx * r[9]));
+}
+
+// f_T = DD3[exp](-2 pi i (t1 + {0, d2, d3})).
+__device__ __forceinline__ void dd3(float t1, float d2, float d3, float& fr, float& fi) {
+  const float lo = fminf(fminf(0.0f, d2), d3);
+  const float hi = fmaxf(fmaxf(0.0f, d2), d3);
+  const float s = hi - lo;
+  if (s < SERIES_REV) {
+    const float m = (d2 + d3) * (1.0f / 3.0f);
+    const float a0 = -TWO_PI_F * m, a1 = TWO_PI_F * (d2 - m), a2 = TWO_PI_F * (d3 - m);
+    const float E2 = fmaf(a0, a1 + a2, a1 * a2);
+    const float E3 = a0 * a1 * a2;
+    const float pre = fmaf(E2, fmaf(E2, fmaf(E2, 2.4801587302e-5f, 1.3888888889e-3f), 4.1666666667e-2f), 0.5f) -
+                      E3 * E3 * 2.4801587302e-5f;
+    const float pim = E3 * fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
+    float c, sn;
+    cis_neg(reduce_rev(t1 + m), c, sn);
+    fr = c * pre - sn * pim;
+    fi = fmaf(c, pim, sn * pre);
+    return;
+  }
+  const float mid = __builtin_amdgcn_fmed3f(0.0f, d2, d3);
+  const float g1 = mid - lo, g2 = hi - mid;
+  const float x1 = PI_F * g1, x2 = PI_F * g2, S = TWO_PI_F * s;
+  const float X1 = fmaxf(x1, 0.5f), X2 = fmaxf(x2, 0.5f);
+  const float rinv = __builtin_amdgcn_rcpf(S * X1 * X2);
+  const float invS = rinv * X1 * X2, invX1 = rinv * S * X2, invX2 = rinv * S * X1;
+  const float sin1 = __builtin_amdgcn_sinf(reduce_rev(0.5f * g1));
+  const float sin2 = __builtin_amdgcn_sinf(reduce_rev(0.5f * g2));
+  const float sg1 = sinc_from(x1, sin1, invX1), sg2 = sinc_from(x2, sin2, invX2);
+  float ch, shn, cp, spn;
+  cis_neg(reduce_rev(0.5f * s), ch, shn);               // e^{-i pi s}
+  cis_neg(reduce_rev(t1 + 0.5f * (lo + mid)), cp, spn);  // phase at the lo-mid midpoint
+  // B = sg2 e^{-i pi s} - sg1 ;  f = G' B (i / S)
+  const float br = fmaf(sg2, ch, -sg1), bi = sg2 * shn;
+  const float gr = cp * br - spn * bi, gi = fmaf(cp, bi, spn * br);
+  fr = -gi * invS;
+  fi = gr * invS;
+}
+
+// f_T and the three DD4_p (repeated node p) in slot order {node 0, d2, d3}.
+struct DD34 {
+  float fr, fi;
+  float dr[3], di[3];
+};
+
+__device__ __forceinline__ void dd34(float t1, float d2, float d3, DD34& o) {
+  const float lo = fminf(fminf(0.0f, d2), d3);
+  const float hi = fmaxf(fmaxf(0.0f, d2), d3);
+  const float s = hi - lo;
+  if (s < SERIES_REV) {
+    const float m = (d2 + d3) * (1.0f / 3.0f);
+    const float a[3] = {-TWO_PI_F * m, TWO_PI_F * (d2 - m), TWO_PI_F * (d3 - m)};
+    const float E2 = fmaf(a[0], a[1] + a[2], a[1] * a[2]);
+    const float E3 = a[0] * a[1] * a[2];
+    const float pre = fmaf(E2, fmaf(E2, fmaf(E2, 2.4801587302e-5f, 1.3888888889e-3f), 4.1666666667e-2f), 0.5f) -
+                      E3 * E3 * 2.4801587302e-5f;
+    const float pim = E3 * fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
+    // d Phi / d e2 and d Phi / d e3 (e2 = -E2, e3 = i E3 of the centred nodes)
+    const float p2r = fmaf(E2, fmaf(E2, -7.4404761905e-5f, -2.7777777778e-3f), -4.1666666667e-2f);
+    const float p2i = -E3 * fmaf(E2, 1.6534391534e-5f, 3.9682539683e-4f);
+    const float p3r = fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
+    const float p3i = E3 * fmaf(E2, 1.6534391534e-6f, 4.9603174603e-5f);
+    float c, sn;
+    cis_neg(reduce_rev(t1 + m), c, sn);
+    o.fr = c * pre - sn * pim;
+    o.fi = fmaf(c, pim, sn * pre);
+    const float third_re = pre * (1.0f / 3.0f), third_im = pim * (1.0f / 3.0f);
+    const float e2_23 = E2 * (2.0f / 3.0f);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const float b = fmaf(a[p], a[p], e2_23);
+      const float ar = third_re - a[p] * p2i - b * p3r;
+      const float ai = fmaf(a[p], p2r, third_im) - b * p3i;
+      o.dr[p] = c * ar - sn * ai;
+      o.di[p] = fmaf(c, ai, sn * ar);
+    }
+    return;
+  }
+  const float mid = __builtin_amdgcn_fmed3f(0.0f, d2, d3);
+  const float g1 = mid - lo, g2 = hi - mid;
+  const float x1 = PI_F * g1, x2 = PI_F * g2, S = TWO_PI_F * s;
+  const float X1 = fmaxf(x1, 0.5f), X2 = fmaxf(x2, 0.5f);
+  const float rinv = __builtin_amdgcn_rcpf(S * X1 * X2);
+  const float invS = rinv * X1 * X2, invX1 = rinv * S * X2, invX2 = rinv * S * X1;
+  float c1, s1n, c2, s2n, cl, sln;
+  cis_neg(reduce_rev(0.5f * g1), c1, s1n);      // h1 = e^{-i pi g1}
+  cis_neg(reduce_rev(0.5f * g2), c2, s2n);      // h2 = e^{-i pi g2}
+  cis_neg(reduce_rev(t1 + lo), cl, sln);        // G_lo
+  const float sg1 = sinc_from(x1, -s1n, invX1), sg2 = sinc_from(x2, -s2n, invX2);
+  // h12 = h1 h2 = e^{-i pi s}
+  const float h12r = c1 * c2 - s1n * s2n, h12i = fmaf(c1, s2n, s1n * c2);
+  // f = G_lo h1 (sg2 h12 - sg1) (i/S)
+  const float br = fmaf(sg2, h12r, -sg1), bi = sg2 * h12i;
+  const float hbr = c1 * br - s1n * bi, hbi = fmaf(c1, bi, s1n * br);
+  const float gbr = cl * hbr - sln * hbi, gbi = fmaf(cl, hbi, sln * hbr);
+  const float fr = -gbi * invS, fi = gbr * invS;
+  // phi2(-i G) = sinc(G/2)^2 / 2 - i psi(G),  psi(G) = (G - sin G) / G^2
+  float psi1, psi2;
+  {
+    const float G = 2.0f * x1, G2 = G * G;
+    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, fmaf(G2, 2.5052108385e-8f, -2.7557319224e-6f),
+                                                    1.9841269841e-4f), -8.3333333333e-3f), 0.16666666667f);
+    const float ig = 0.5f * invX1;
+    const float big = (G - 2.0f * (-s1n) * c1) * ig * ig;
+    psi1 = x1 < 0.5f ? ser : big;
+  }
+  {
+    const float G = 2.0f * x2, G2 = G * G;
+    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, fmaf(G2, 2.5052108385e-8f, -2.7557319224e-6f),
+                                                    1.9841269841e-4f), -8.3333333333e-3f), 0.16666666667f);
+    const float ig = 0.5f * invX2;
+    const float big = (G - 2.0f * (-s2n) * c2) * ig * ig;
+    psi2 = x2 < 0.5f ? ser : big;
+  }
+  const float p1r = 0.5f * sg1 * sg1, p1i = -psi1;
+  const float p2r = 0.5f * sg2 * sg2, p2i = -psi2;
+  // D_lo = (i/S) (f - G_lo phi2_1)
+  const float gl1r = cl * p1r - sln * p1i, gl1i = fmaf(cl, p1i, sln * p1r);
+  const float ulr = fr - gl1r, uli = fi - gl1i;
+  // D_hi = (i/S) (G_lo e^{-iS} conj(phi2_2) - f),  e^{-iS} = h12^2
+  const float eSr = h12r * h12r - h12i * h12i, eSi = 2.0f * h12r * h12i;
+  const float gSr = cl * eSr - sln * eSi, gSi = fmaf(cl, eSi, sln * eSr);
+  const float uhr = fmaf(gSr, p2r, gSi * p2i) - fr;        // (gS)(p2r - i p2i)
+  const float uhi = gSi * p2r - gSr * p2i - fi;
+  // D_mid = (i/S) G_lo e^{-i G1} (phi2_2 - conj(phi2_1)),  e^{-iG1} = h1^2
+  const float e1r = c1 * c1 - s1n * s1n, e1i = 2.0f * c1 * s1n;
+  const float g1r = cl * e1r - sln * e1i, g1i = fmaf(cl, e1i, sln * e1r);
+  const float qr = p2r - p1r, qi = p2i + p1i;
+  const float umr = g1r * qr - g1i * qi, umi = fmaf(g1r, qi, g1i * qr);
+  // multiply by i/S: (x + iy) i / S = (-y + i x) / S
+  const float Dlor = -uli * invS, Dloi = ulr * invS;
+  const float Dhir = -uhi * invS, Dhii = uhr * invS;
+  const float Dmir = -umi * invS, Dmii = umr * invS;
+  o.fr = fr;
+  o.fi = fi;
+  const float v[3] = {0.0f, d2, d3};
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const bool is_lo = v[p] == lo, is_hi = v[p] == hi;
+    o.dr[p] = is_lo ? Dlor : (is_hi ? Dhir : Dmir);
+    o.di[p] = is_lo ? Dloi : (is_hi ? Dhii : Dmii);
+  }
+}
+
+// ------------------------------------------------------------- the band
+__device__ __forceinline__ int fft_freq(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+#pragma clang fp contract(off)
+__device__ __noinline__ double band_q(const double* S, const GridC& g, double kx, double ky, double kz) {
+  const double x = (TWO_PI_D * kx) / g.L[0];
+  const double y = (TWO_PI_D * ky) / g.L[1];
+  const double z = (TWO_PI_D * kz) / g.L[2];
+  double q = (S[0] * x) * x;
+  q = q + (S[1] * y) * y;
+  q = q + (S[2] * z) * z;
+  q = q + 2.0 * ((S[3] * x) * y);
+  q = q + 2.0 * ((S[4] * x) * z);
+  q = q + 2.0 * ((S[5] * y) * z);
+  return q;
+}
+#pragma clang fp contract(on)
+
+struct Sig6 {
+  double s[6];
+};
+
+// Bricks of 4x4x4 positions of the half spectrum, brick-major order: the 64
+// entries of a wave stay close in frequency space.
+__device__ __forceinline__ bool slot_pos(const GridC& g, int64_t slot, int& ix, int& iy, int& iz) {
+  const int64_t b = slot >> 6;
+  const int w = (int)(slot & 63);
+  const int nbz = (g.n2h + 3) >> 2, nby = (g.n1 + 3) >> 2;
+  const int bz = (int)(b % nbz);
+  const int64_t r = b / nbz;
+  const int by = (int)(r % nby);
+  const int bx = (int)(r / nby);
+  ix = bx * 4 + (w >> 4);
+  iy = by * 4 + ((w >> 2) & 3);
+  iz = bz * 4 + (w & 3);
+  return ix < g.n0 && iy < g.n1 && iz < g.n2h;
+}
+
+struct Aliases {
+  int n;                 // 1 or 2
+  int k[2][3];
+};
+
+__device__ __forceinline__ Aliases aliases_of(const GridC& g, int ix, int iy, int iz) {
+  Aliases a;
+  const int kx = fft_freq(ix, g.n0), ky = fft_freq(iy, g.n1);
+  const bool nz_even = (g.n2 & 1) == 0;
+  const int kz = (nz_even && iz == g.n2 / 2) ? -iz : iz;
+  const bool nyx = (g.n0 & 1) == 0 && ix == g.n0 / 2;
+  const bool nyy = (g.n1 & 1) == 0 && iy == g.n1 / 2;
+  const bool nyz = nz_even && iz == g.n2 / 2;
+  a.k[0][0] = kx;
+  a.k[0][1] = ky;
+  a.k[0][2] = kz;
+  a.n = (nyx || nyy || nyz) ? 2 : 1;
+  a.k[1][0] = nyx ? -kx : kx;
+  a.k[1][1] = nyy ? -ky : ky;
+  a.k[1][2] = nyz ? -kz : kz;
+  return a;
+}
+
+__global__ void k_band_count(GridC g, Sig6 S, double qmax, int32_t* __restrict__ cnt, int64_t n_slots) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= n_slots) return;
+  int ix, iy, iz;
+  int c = 0;
+  if (slot_pos(g, slot, ix, iy, iz)) {
+    const Aliases a = aliases_of(g, ix, iy, iz);
+    for (int j = 0; j < a.n; ++j)
+      c += band_q(S.s, g, a.k[j][0], a.k[j][1], a.k[j][2]) < qmax ? 1 : 0;
+  }
+  cnt[slot] = c;
+}
+
+__global__ void k_band_fill(GridC g, Sig6 S, double qmax, const int32_t* __restrict__ cnt,
+                            const int32_t* __restrict__ off, int64_t n_slots, BandDev b) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= n_slots) return;
+  int ix, iy, iz;
+  if (!slot_pos(g, slot, ix, iy, iz)) return;
+  const int p = (ix * g.n1 + iy) * g.n2h + iz;
+  const int c = cnt[slot];
+  if (c == 0) {
+    b.map[p] = -1;
+    return;
+  }
+  const int e0 = off[slot];
+  b.map[p] = e0 | ((c - 1) << 30);
+  const Aliases a = aliases_of(g, ix, iy, iz);
+  int e = e0;
+  for (int j = 0; j < a.n; ++j) {
+    const double q = band_q(S.s, g, a.k[j][0], a.k[j][1], a.k[j][2]);
+    if (!(q < qmax)) continue;
+    b.kf[e] = make_float4((float)a.k[j][0], (float)a.k[j][1], (float)a.k[j][2], (float)exp(-0.5 * q));
+    b.wgt[e] = a.n == 2 ? 0.5f : 1.0f;
+    b.pos[e] = p;
+    ++e;
+  }
+}
+
+// ------------------------------------------------------------- scan (int32)
+constexpr int SCAN_T = 256, SCAN_PER = 4, SCAN_BLK = SCAN_T * SCAN_PER;
+
+__device__ int block_excl_scan(int v, int* sh, int& total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < SCAN_T; o <<= 1) {
+    const int add = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  total = sh[SCAN_T - 1];
+  const int incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t* __restrict__ in, int64_t n,
+                                                          int32_t* __restrict__ bsum) {
+  __shared__ int sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLK + threadIdx.x * SCAN_PER;
+  int v = 0;
+  for (int j = 0; j < SCAN_PER; ++j)
+    if (base + j < n) v += in[base + j];
+  int total;
+  block_excl_scan(v, sh, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_top(int32_t* __restrict__ bsum, int64_t nb,
+                                                       int64_t* __restrict__ total_out) {
+  __shared__ int sh[SCAN_T];
+  const int64_t per = (nb + SCAN_T - 1) / SCAN_T;
+  const int64_t b0 = threadIdx.x * per;
+  int v = 0;
+  for (int64_t j = 0; j < per; ++j)
+    if (b0 + j < nb) v += bsum[b0 + j];
+  int total;
+  int run = block_excl_scan(v, sh, total);
+  for (int64_t j = 0; j < per; ++j)
+    if (b0 + j < nb) {
+      const int x = bsum[b0 + j];
+      bsum[b0 + j] = run;
+      run += x;
+    }
+  if (threadIdx.x == 0) *total_out = total;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                         int64_t n, const int32_t* __restrict__ bsum) {
+  __shared__ int sh[SCAN_T];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLK + threadIdx.x * SCAN_PER;
+  int v[SCAN_PER];
+  int s = 0;
+  for (int j = 0; j < SCAN_PER; ++j) {
+    v[j] = base + j < n ? in[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int run = block_excl_scan(s, sh, total) + bsum[blockIdx.x];
+  for (int j = 0; j < SCAN_PER; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+}
+
+// --------------------------------------------------------------- mesh prep
+constexpr int PREP_T = 256;
+
+template <typename T>
+__device__ T block_sum(T v, T* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = PREP_T / 2; o > 0; o >>= 1) {
+    if (t < o) sh[t] += sh[t + o];
+    __syncthreads();
+  }
+  const T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(PREP_T) k_prep_centroid(GridC g, const float* __restrict__ V, int nv,
+                                                            MeshInfo* __restrict__ info) {
+  __shared__ double sh[PREP_T];
+  double a[3] = {0, 0, 0};
+  for (int i = threadIdx.x; i < nv; i += PREP_T)
+    for (int j = 0; j < 3; ++j) a[j] += (double)V[3 * i + j];
+  double c[3];
+  for (int j = 0; j < 3; ++j) c[j] = block_sum(a[j], sh) / (double)(nv > 0 ? nv : 1);
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < 3; ++j) {
+      info->c[j] = (float)c[j];
+      info->cu[j] = ((double)(float)c[j] - g.origin[j]) / g.L[j];
+    }
+    info->pad0 = 0.0f;
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __restrict__ V,
+                                                        const int32_t* __restrict__ F, int nt,
+                                                        const MeshInfo* __restrict__ info,
+                                                        float* __restrict__ rec, double* __restrict__ tmp) {
+  __shared__ double sh[PREP_T];
+  double area = 0.0, vol = 0.0;
+  const double c[3] = {(double)info->c[0], (double)info->c[1], (double)info->c[2]};
+  for (int t = blockIdx.x * PREP_T + threadIdx.x; t < nt; t += gridDim.x * PREP_T) {
+    double v[3][3];
+    for (int p = 0; p < 3; ++p) {
+      const int vi = F[3 * t + p];
+      for (int j = 0; j < 3; ++j) v[p][j] = (double)V[3 * vi + j];
+    }
+    float* r = rec + (size_t)t * TRI_REC;
+    double e2[3], e3[3], a[3], b[3];
+    for (int j = 0; j < 3; ++j) {
+      const double u = (v[0][j] - c[j]) / g.L[j];
+      const double uh = rint(u * (double)PHASE_GRID) / (double)PHASE_GRID;
+      r[j] = (float)uh;
+      r[3 + j] = (float)(u - uh);
+      e2[j] = v[1][j] - v[0][j];
+      e3[j] = v[2][j] - v[0][j];
+      r[6 + j] = (float)(e2[j] / g.L[j]);
+      r[9 + j] = (float)(e3[j] / g.L[j]);
+      a[j] = v[1][j] - c[j];
+      b[j] = v[2][j] - c[j];
+    }
+    const double n[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2], e2[0] * e3[1] - e2[1] * e3[0]};
+    const double twoA = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (MODE == 0) {
+      for (int j = 0; j < 3; ++j) r[12 + j] = (float)(n[j] / g.L[j]);
+    } else {
+      r[12] = (float)twoA;
+      r[13] = 0.0f;
+      r[14] = 0.0f;
+    }
+    r[15] = 0.0f;
+    area += 0.5 * twoA;
+    const double a0[3] = {v[0][0] - c[0], v[0][1] - c[1], v[0][2] - c[2]};
+    vol += (a0[0] * (a[1] * b[2] - a[2] * b[1]) + a0[1] * (a[2] * b[0] - a[0] * b[2]) +
+            a0[2] * (a[0] * b[1] - a[1] * b[0])) / 6.0;
+  }
+  area = block_sum(area, sh);
+  vol = block_sum(vol, sh);
+  if (threadIdx.x == 0) {
+    tmp[2 * blockIdx.x] = area;
+    tmp[2 * blockIdx.x + 1] = vol;
+  }
+}
+
+__global__ void __launch_bounds__(PREP_T) k_prep_totals(const double* __restrict__ tmp, int nblk,
+                                                          MeshInfo* __restrict__ info) {
+  __shared__ double sh[PREP_T];
+  double a = 0.0, v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += PREP_T) {
+    a += tmp[2 * i];
+    v += tmp[2 * i + 1];
+  }
+  a = block_sum(a, sh);
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    info->area = a;
+    info->volume = v;
+  }
+}
+
+// ------------------------------------------------------------ forward sweep
+constexpr int SWEEP_T = 256;
+
+template <int MODE>
+__global__ void __launch_bounds__(SWEEP_T) k_fwd_sweep(const float4* __restrict__ kf, int nE,
+                                                         const float* __restrict__ rec, int nt, int tpc,
+                                                         float2* __restrict__ part) {
+  const int e = blockIdx.x * SWEEP_T + threadIdx.x;
+  const int t0 = blockIdx.y * tpc;
+  const int t1 = min(nt, t0 + tpc);
+  float kx = 0.0f, ky = 0.0f, kz = 0.0f;
+  if (e < nE) {
+    const float4 q = kf[e];
+    kx = q.x;
+    ky = q.y;
+    kz = q.z;
+  }
+  float ar = 0.0f, ai = 0.0f;
+  for (int t = t0; t < t1; ++t) {
+    const float* r = rec + (size_t)t * TRI_REC;
+    float tv, d2, d3, fr, fi;
+    tri_phases(kx, ky, kz, r, tv, d2, d3);
+    dd3(tv, d2, d3, fr, fi);
+    const float w = MODE == 0 ? fmaf(kz, r[14], fmaf(ky, r[13], kx * r[12])) : r[12];
+    ar = fmaf(w, fr, ar);
+    ai = fmaf(w, fi, ai);
+  }
+  if (e < nE) part[(size_t)blockIdx.y * nE + e] = make_float2(ar, ai);
+}
+
+// Phase factor e^{-i xi.(c - origin)} for integer frequency k (float32 after
+// an exact float64 reduction).
+__device__ __forceinline__ void ref_phase(const MeshInfo* info, float kx, float ky, float kz, float& pr,
+                                          float& pi) {
+  double t = (double)kx * info->cu[0] + (double)ky * info->cu[1] + (double)kz * info->cu[2];
+  t -= rint(t);
+  cis_neg((float)t, pr, pi);
+}
+
+// u_hat at one band entry from the summed sweep value.
+template <int MODE>
+__device__ __forceinline__ float2 finish_u(const GridC& g, const MeshInfo* info, float kx, float ky, float kz,
+                                           float sr, float si) {
+  float pr, pi;
+  ref_phase(info, kx, ky, kz, pr, pi);
+  const float zr = pr * sr - pi * si, zi = fmaf(pr, si, pi * sr);
+  if (MODE == 0) {
+    if (kx == 0.0f && ky == 0.0f && kz == 0.0f) return make_float2((float)info->volume, 0.0f);
+    const float xx = kx * g.two_pi_over_L[0], xy = ky * g.two_pi_over_L[1], xz = kz * g.two_pi_over_L[2];
+    const float q2 = fmaf(xz, xz, fmaf(xy, xy, xx * xx));
+    const float f = TWO_PI_F / q2;   // u = i (2 pi / |xi|^2) z
+    return make_float2(-zi * f, zr * f);
+  }
+  const float ia = (float)(1.0 / info->area);
+  return make_float2(zr * ia, zi * ia);
+}
+
+template <int MODE>
+__global__ void k_fwd_finalize(GridC g, BandDev b, const float2* __restrict__ part, int n_chunks,
+                               const MeshInfo* __restrict__ info, float2* __restrict__ spec_out,
+                               float2* __restrict__ xhalf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.n_pos) return;
+  const int32_t m = b.map[p];
+  float xr = 0.0f, xi = 0.0f;
+  if (m >= 0) {
+    const int e0 = m & 0x3fffffff, cntm1 = (m >> 30) & 1;
+    for (int e = e0; e <= e0 + cntm1; ++e) {
+      float sr = 0.0f, si = 0.0f;
+      for (int c = 0; c < n_chunks; ++c) {
+        const float2 v = part[(size_t)c * b.n_entries + e];
+        sr += v.x;
+        si += v.y;
+      }
+      const float4 k = b.kf[e];
+      const float2 u = finish_u<MODE>(g, info, k.x, k.y, k.z, sr, si);
+      if (spec_out) spec_out[e] = u;
+      const float hw = k.w * b.wgt[e];
+      xr = fmaf(hw, u.x, xr);
+      xi = fmaf(hw, u.y, xi);
+    }
+  }
+  if (xhalf) xhalf[p] = make_float2(xr * g.inv_LV, xi * g.inv_LV);
+}
+
+__global__ void k_spec_scatter(GridC g, BandDev b, const float2* __restrict__ spec, float2* __restrict__ xhalf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.n_pos) return;
+  const int32_t m = b.map[p];
+  float xr = 0.0f, xi = 0.0f;
+  if (m >= 0) {
+    const int e0 = m & 0x3fffffff, cntm1 = (m >> 30) & 1;
+    for (int e = e0; e <= e0 + cntm1; ++e) {
+      const float hw = b.kf[e].w * b.wgt[e];
+      xr = fmaf(hw, spec[e].x, xr);
+      xi = fmaf(hw, spec[e].y, xi);
+    }
+  }
+  xhalf[p] = make_float2(xr * g.inv_LV, xi * g.inv_LV);
+}
+
+// ------------------------------------------------------- adjoint weights
+constexpr int ADJ_T = 256;
+
+template <int MODE>
+__global__ void __launch_bounds__(ADJ_T) k_adjoint(GridC g, BandDev b, const float2* __restrict__ ghat,
+                                                     const MeshInfo* __restrict__ info,
+                                                     const float2* __restrict__ spec, float4* __restrict__ erec,
+                                                     double* __restrict__ dsig_part) {
+  __shared__ double sh[ADJ_T];
+  double d6[6] = {0, 0, 0, 0, 0, 0};
+  const float inv_area = MODE == 1 ? (float)(1.0 / info->area) : 1.0f;
+  for (int64_t p = (int64_t)blockIdx.x * ADJ_T + threadIdx.x; p < b.n_pos; p += (int64_t)gridDim.x * ADJ_T) {
+    const int32_t m = b.map[p];
+    if (m < 0) continue;
+    const int iz = (int)(p % g.n2h);
+    const float cp = (iz == 0 || ((g.n2 & 1) == 0 && iz == g.n2 / 2)) ? 1.0f : 2.0f;
+    const float2 G = ghat[p];
+    const int e0 = m & 0x3fffffff, cntm1 = (m >> 30) & 1;
+    for (int e = e0; e <= e0 + cntm1; ++e) {
+      const float4 k = b.kf[e];
+      const float base = cp * b.wgt[e] * k.w * g.inv_LV;
+      float pr, pi;
+      ref_phase(info, k.x, k.y, k.z, pr, pi);
+      // W = base conj(G) phase [/ area]
+      const float a = base * inv_area;
+      const float wr = a * (G.x * pr + G.y * pi);
+      const float wi = a * (G.x * pi - G.y * pr);
+      const float xx = k.x * g.two_pi_over_L[0], xy = k.y * g.two_pi_over_L[1], xz = k.z * g.two_pi_over_L[2];
+      erec[2 * e] = make_float4(k.x, k.y, k.z, wr);
+      erec[2 * e + 1] = make_float4(wi, xx, xy, xz);
+      if (dsig_part) {
+        const float2 u = spec[e];
+        const double val = (double)base * (double)(G.x * u.x + G.y * u.y);
+        const double X = xx, Y = xy, Z = xz;
+        d6[0] += val * (-0.5 * X * X);
+        d6[1] += val * (-0.5 * Y * Y);
+        d6[2] += val * (-0.5 * Z * Z);
+        d6[3] += val * (-X * Y);
+        d6[4] += val * (-X * Z);
+        d6[5] += val * (-Y * Z);
+      }
+    }
+  }
+  if (dsig_part) {
+    for (int j = 0; j < 6; ++j) {
+      sh[threadIdx.x] = d6[j];
+      __syncthreads();
+      for (int o = ADJ_T / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) dsig_part[6 * blockIdx.x + j] = sh[0];
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64) k_dsig_final(const double* __restrict__ part, int nblk, float* __restrict__ out) {
+  __shared__ double sh[6][64];
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nblk; i += 64)
+    for (int j = 0; j < 6; ++j) a[j] += part[6 * i + j];
+  for (int j = 0; j < 6; ++j) sh[j][threadIdx.x] = a[j];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double s = 0.0;
+    for (int i = 0; i < 64; ++i) s += sh[threadIdx.x][i];
+    out[threadIdx.x] = (float)s;
+  }
+}
+
+// --------------------------------------------------------------- VJP sweep
+template <int MODE>
+__global__ void __launch_bounds__(SWEEP_T) k_vjp_sweep(const float* __restrict__ rec, int nt,
+                                                         const float4* __restrict__ erec, int nE, int epc,
+                                                         float* __restrict__ part) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
+  const int t = blockIdx.x * SWEEP_T + threadIdx.x;
+  const int e0 = blockIdx.y * epc;
+  const int e1 = min(nE, e0 + epc);
+  float r[12];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) r[j] = 0.0f;
+  if (t < nt) {
+    const float4* rr = reinterpret_cast<const float4*>(rec + (size_t)t * TRI_REC);
+    const float4 a = rr[0], bq = rr[1], c = rr[2];
+    r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
+    r[4] = bq.x; r[5] = bq.y; r[6] = bq.z; r[7] = bq.w;
+    r[8] = c.x; r[9] = c.y; r[10] = c.z; r[11] = c.w;
+  }
+  float acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = 0.0f;
+  for (int e = e0; e < e1; ++e) {
+    const float4 A = erec[2 * e], B = erec[2 * e + 1];
+    float tv, d2, d3;
+    tri_phases(A.x, A.y, A.z, r, tv, d2, d3);
+    DD34 o;
+    dd34(tv, d2, d3, o);
+    const float wr = A.w, wi = B.x;
+    if (MODE == 0) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) acc[p] = fmaf(wr, o.dr[p], fmaf(-wi, o.di[p], acc[p]));
+    } else {
+      acc[0] = fmaf(wr, o.fr, fmaf(-wi, o.fi, acc[0]));
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const float im = fmaf(wr, o.di[p], wi * o.dr[p]);
+        acc[1 + 3 * p] = fmaf(im, B.y, acc[1 + 3 * p]);
+        acc[2 + 3 * p] = fmaf(im, B.z, acc[2 + 3 * p]);
+        acc[3 + 3 * p] = fmaf(im, B.w, acc[3 + 3 * p]);
+      }
+    }
+  }
+  if (t < nt) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) part[((size_t)blockIdx.y * NC + j) * nt + t] = acc[j];
+  }
+}
+
+__global__ void k_vjp_reduce(const float* __restrict__ part, int n_chunks, int nc, int nt, float* __restrict__ red) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)nc * nt;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * n + i];
+  red[i] = s;
+}
+
+// R = (1/|Lambda|) sum_T 2 A_T s_T  (surface normalisation term of Eq. 6)
+__global__ void __launch_bounds__(PREP_T) k_surface_scalar(const float* __restrict__ red,
+                                                             const float* __restrict__ rec, int nt,
+                                                             const MeshInfo* __restrict__ info,
+                                                             double* __restrict__ out) {
+  __shared__ double sh[PREP_T];
+  double a = 0.0;
+  for (int t = threadIdx.x; t < nt; t += PREP_T) a += (double)rec[(size_t)t * TRI_REC + 12] * (double)red[t];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) *out = a / info->area;
+}
+
+template <int MODE>
+__global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32_t* __restrict__ F, int nt,
+                                const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
+                                const float* __restrict__ red, const double* __restrict__ Rp,
+                                float* __restrict__ dV) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const float R = MODE == 1 ? (float)(*Rp) : 0.0f;
+  float g[3] = {0.0f, 0.0f, 0.0f};
+  for (int i = off[v]; i < off[v + 1]; ++i) {
+    const int tp = ent[i];
+    const int t = tp / 3, p = tp - 3 * t;
+    float x[3][3];
+    for (int q = 0; q < 3; ++q) {
+      const int vi = F[3 * t + q];
+      for (int j = 0; j < 3; ++j) x[q][j] = V[3 * vi + j];
+    }
+    const float a[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+    const float b[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+    const float n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    if (MODE == 0) {
+      const float Q = red[(size_t)p * nt + t];
+      for (int j = 0; j < 3; ++j) g[j] = fmaf(n[j], Q, g[j]);
+    } else {
+      const float twoA = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      const float inv = twoA > 0.0f ? 1.0f / twoA : 0.0f;
+      const float N[3] = {n[0] * inv, n[1] * inv, n[2] * inv};
+      const int pm = (p + 2) % 3, pp = (p + 1) % 3;
+      const float ep[3] = {x[pm][0] - x[pp][0], x[pm][1] - x[pp][1], x[pm][2] - x[pp][2]};
+      const float w[3] = {ep[1] * N[2] - ep[2] * N[1], ep[2] * N[0] - ep[0] * N[2], ep[0] * N[1] - ep[1] * N[0]};
+      const float s = red[t];
+      for (int j = 0; j < 3; ++j) {
+        const float P = red[(size_t)(1 + 3 * p + j) * nt + t];
+        g[j] += twoA * P - w[j] * s + 0.5f * R * w[j];
+      }
+    }
+  }
+  for (int j = 0; j < 3; ++j) dV[3 * v + j] = g[j];
+}
+
+// ------------------------------------------------------ arbitrary points
+__global__ void k_points_prepare(const int32_t* __restrict__ k, int64_t n, float4* __restrict__ kf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  kf[i] = make_float4((float)k[3 * i], (float)k[3 * i + 1], (float)k[3 * i + 2], 1.0f);
+}
+
+template <int MODE>
+__global__ void k_points_finalize(GridC g, const float4* __restrict__ kf, int64_t n, const float2* __restrict__ part,
+                                  int n_chunks, const MeshInfo* __restrict__ info, float2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float sr = 0.0f, si = 0.0f;
+  for (int c = 0; c < n_chunks; ++c) {
+    const float2 v = part[(size_t)c * n + i];
+    sr += v.x;
+    si += v.y;
+  }
+  const float4 k = kf[i];
+  out[i] = finish_u<MODE>(g, info, k.x, k.y, k.z, sr, si);
+}
+
+__global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_count(const GridC& g, const double* sigma6, double qmax, int32_t* cnt, int64_t n_slots,
+                             hipStream_t s) {
+  Sig6 S;
+  for (int j = 0; j < 6; ++j) S.s[j] = sigma6[j];
+  hipLaunchKernelGGL(k_band_count, dim3(blocks_for(n_slots, 256)), dim3(256), 0, s, g, S, qmax, cnt, n_slots);
+  return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + SCAN_BLK - 1) / SCAN_BLK + 1; }
+
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* block_tmp, int64_t* total,
+                       hipStream_t s) {
+  const int64_t nb = (n + SCAN_BLK - 1) / SCAN_BLK;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, block_tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, s, block_tmp, nb, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, (const int32_t*)block_tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_fill(const GridC& g, const double* sigma6, double qmax, const int32_t* cnt,
+                            const int32_t* off, int64_t n_slots, BandDev b, hipStream_t s) {
+  Sig6 S;
+  for (int j = 0; j < 6; ++j) S.s[j] = sigma6[j];
+  hipLaunchKernelGGL(k_band_fill, dim3(blocks_for(n_slots, 256)), dim3(256), 0, s, g, S, qmax, cnt, off, n_slots, b);
+  return hipGetLastError();
+}
+
+int mesh_prep_blocks(int nt) {
+  int b = (nt + PREP_T - 1) / PREP_T;
+  return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces, int nt,
+                            float* tri_rec, MeshInfo* info, double* block_tmp, int tmp_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_centroid, dim3(1), dim3(PREP_T), 0, s, g, verts, nv, info);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_prep_tris<0>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, nt,
+                       (const MeshInfo*)info, tri_rec, block_tmp);
+  else
+    hipLaunchKernelGGL(k_prep_tris<1>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, nt,
+                       (const MeshInfo*)info, tri_rec, block_tmp);
+  hipLaunchKernelGGL(k_prep_totals, dim3(1), dim3(PREP_T), 0, s, (const double*)block_tmp, tmp_blocks, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_sweep(int mode, const float4* kf, int64_t nE, const float* tri_rec, int nt,
+                            int tris_per_chunk, int n_chunks, float2* part, hipStream_t s) {
+  const dim3 grid(blocks_for(nE, SWEEP_T), (unsigned)n_chunks);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_fwd_sweep<0>, grid, dim3(SWEEP_T), 0, s, kf, (int)nE, tri_rec, nt, tris_per_chunk, part);
+  else
+    hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(SWEEP_T), 0, s, kf, (int)nE, tri_rec, nt, tris_per_chunk, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_finalize(int mode, const GridC& g, BandDev b, const float2* part, int n_chunks,
+                               const MeshInfo* info, float2* spec_out, float2* xhalf, hipStream_t s) {
+  const dim3 grid(blocks_for(b.n_pos, 256));
+  if (mode == 0)
+    hipLaunchKernelGGL(k_fwd_finalize<0>, grid, dim3(256), 0, s, g, b, part, n_chunks, info, spec_out, xhalf);
+  else
+    hipLaunchKernelGGL(k_fwd_finalize<1>, grid, dim3(256), 0, s, g, b, part, n_chunks, info, spec_out, xhalf);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec_scatter(const GridC& g, BandDev b, const float2* spec, float2* xhalf, hipStream_t s) {
+  hipLaunchKernelGGL(k_spec_scatter, dim3(blocks_for(b.n_pos, 256)), dim3(256), 0, s, g, b, spec, xhalf);
+  return hipGetLastError();
+}
+
+int adjoint_blocks(const GridC& g) {
+  const int64_t npos = (int64_t)g.n0 * g.n1 * g.n2h;
+  int64_t b = (npos + ADJ_T - 1) / ADJ_T;
+  if (b > 2048) b = 2048;
+  return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_adjoint(int mode, const GridC& g, BandDev b, const float2* ghat, const MeshInfo* info,
+                          const float2* spec, float4* erec, double* dsig_part, int dsig_blocks, hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k_adjoint<0>, dim3(dsig_blocks), dim3(ADJ_T), 0, s, g, b, ghat, info, spec, erec, dsig_part);
+  else
+    hipLaunchKernelGGL(k_adjoint<1>, dim3(dsig_blocks), dim3(ADJ_T), 0, s, g, b, ghat, info, spec, erec, dsig_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hipStream_t s) {
+  hipLaunchKernelGGL(k_dsig_final, dim3(1), dim3(64), 0, s, dsig_part, nblk, out6);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_sweep(int mode, const float* tri_rec, int nt, const float4* erec, int64_t nE,
+                            int ents_per_chunk, int n_chunks, float* part, hipStream_t s) {
+  const dim3 grid(blocks_for(nt, SWEEP_T), (unsigned)n_chunks);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_vjp_sweep<0>, grid, dim3(SWEEP_T), 0, s, tri_rec, nt, erec, (int)nE, ents_per_chunk, part);
+  else
+    hipLaunchKernelGGL(k_vjp_sweep<1>, grid, dim3(SWEEP_T), 0, s, tri_rec, nt, erec, (int)nE, ents_per_chunk, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* red, hipStream_t s) {
+  const int nc = nchannels(mode);
+  hipLaunchKernelGGL(k_vjp_reduce, dim3(blocks_for((int64_t)nc * nt, 256)), dim3(256), 0, s, part, n_chunks, nc, nt,
+                     red);
+  return hipGetLastError();
+}
+
+hipError_t launch_surface_scalar(const float* red, const float* tri_rec, int nt, const MeshInfo* info,
+                                 double* out_R, hipStream_t s) {
+  hipLaunchKernelGGL(k_surface_scalar, dim3(1), dim3(PREP_T), 0, s, red, tri_rec, nt, info, out_R);
+  return hipGetLastError();
+}
+
+hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, int nt,
+                                const int32_t* csr_off, const int32_t* csr_ent, const float* red,
+                                const double* R, float* dV, hipStream_t s) {
+  const dim3 grid(blocks_for(nv, 128));
+  if (mode == 0)
+    hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(128), 0, s, verts, nv, faces, nt, csr_off, csr_ent, red, R, dV);
+  else
+    hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(128), 0, s, verts, nv, faces, nt, csr_off, csr_ent, red, R, dV);
+  return hipGetLastError();
+}
+
+hipError_t launch_points_prepare(const GridC& g, const int32_t* k, int64_t n, float4* kf, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_points_prepare, dim3(blocks_for(n, 256)), dim3(256), 0, s, k, n, kf);
+  return hipGetLastError();
+}
+
+hipError_t launch_points_finalize(int mode, const GridC& g, const float4* kf, int64_t n, const float2* part,
+                                  int n_chunks, const MeshInfo* info, float2* out, hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k_points_finalize<0>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, kf, n, part, n_chunks, info,
+                       out);
+  else
+    hipLaunchKernelGGL(k_points_finalize<1>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, kf, n, part, n_chunks, info,
+                       out);
+  return hipGetLastError();
+}
+
+}  // namespace dm
