@@ -178,12 +178,103 @@ dm_status dm_render_vjp(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, co
 dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev,
                             int64_t n, float* out_dev, void* stream);
 
+/* ----------------------------------------------------------------- batch */
+
+/* One request of a batch: the forward render and/or gradient of one mesh on
+ * its own grid with its own PSF (same meaning as dm_render_vjp's arguments).
+ * dL_dimage_dev may be NULL for a forward-only request; any output may be
+ * NULL, but each request must ask for at least one. */
+typedef struct {
+  dm_mesh mesh;
+  dm_psf psf;
+  dm_grid grid;
+  const float* dL_dimage_dev;   /* [n0][n1][n2] or NULL */
+  float* image_dev;             /* [n0][n1][n2] or NULL */
+  float* dL_dverts_dev;         /* [n_verts][3] or NULL (needs dL_dimage_dev) */
+  float* dL_dsigma_dev;         /* [6] or NULL (needs dL_dimage_dev) */
+} dm_request;
+
+/* Runs n independent requests of uneven sizes and grids as one batch: the
+ * mesh-transform sweeps of all of them (forward, Eq. 5/7-8, and gradient,
+ * Eq. 6/9-10) execute in one persistent launch whose workgroups draw work
+ * tiles from a shared queue, longest first; the small per-request steps
+ * (band, mesh prep, FFTs, adjoint weights, reductions) run around it on the
+ * same stream.  Each request's tiles and summation order depend on that
+ * request alone, so its results are bitwise the same whatever else is in the
+ * batch (and agree with dm_render_vjp to rounding).  All validation happens
+ * before anything is enqueued; on error no output is written. */
+dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* stream);
+
+/* --------------------------------------------------------------- serving */
+
+/* A continuous-batching server for render + gradient requests on many
+ * independent meshes.  A worker thread owns its own handle.  Meshes are made
+ * resident once (dm_server_mesh_add); requests name a resident mesh and carry
+ * their own PSF, grid and device buffers.  Whenever one of max_inflight stream
+ * slots is free, the worker admits queued requests in arrival order, as many
+ * as max_batch and the HBM budget allow (a request's footprint is its
+ * workspace: band-sized partials, spectra, FFT buffers), and launches them
+ * as one batch (the dm_batch_run machinery, workspace from the stream-ordered
+ * allocator); requests that arrive meanwhile join the next batch, which runs
+ * while the earlier ones are still on the GPU.  Results are bitwise
+ * independent of which requests shared a batch.  Thread-safe: any thread may
+ * submit and poll. */
+typedef struct dm_server dm_server;
+
+typedef struct {
+  int32_t max_batch;          /* most requests launched together (>= 1) */
+  int32_t max_inflight;       /* batches on the GPU at once, one stream each (1..8) */
+  int32_t queue_capacity;     /* queued requests beyond this: DM_ERR_BUSY (>= 1) */
+  size_t hbm_budget_bytes;    /* cap on the summed footprint of in-flight batches (0 = none) */
+} dm_server_config;
+
+typedef struct {
+  int32_t mesh_id;            /* from dm_server_mesh_add */
+  dm_psf psf;
+  dm_grid grid;
+  const float* dL_dimage_dev; /* [n0][n1][n2], or NULL for a forward-only request */
+  float* image_dev;           /* outputs as in dm_request; device buffers owned by */
+  float* dL_dverts_dev;       /* the caller and kept valid until dm_poll reports  */
+  float* dL_dsigma_dev;       /* the request finished                            */
+} dm_serve_request;
+
+typedef struct {
+  dm_status status;           /* DM_OK, or why the request failed (DM_ERR_BUDGET: */
+                              /* its footprint alone exceeds the budget)          */
+  int32_t batch_size;         /* requests in the batch that carried it */
+  double queue_ms;            /* submission to launch */
+  double total_ms;            /* submission to completion seen by the server */
+} dm_serve_result;
+
+typedef struct {
+  int64_t submitted, completed, rejected, batches;
+  double mean_batch;
+  size_t peak_inflight_bytes;
+} dm_server_stats;
+
+dm_status dm_server_create(int device, const dm_server_config* cfg, dm_server** out);
+/* Finishes every queued and in-flight request, then frees everything. */
+dm_status dm_server_destroy(dm_server* s);
+/* Uploads a mesh (host arrays) and validates its faces; DM_ERR_MESH as for
+ * dm_topology_create. */
+dm_status dm_server_mesh_add(dm_server* s, const float* verts_host, int32_t n_verts, const int32_t* faces_host,
+                             int32_t n_faces, int32_t* mesh_id);
+/* DM_ERR_STATE while requests on the mesh are pending. */
+dm_status dm_server_mesh_remove(dm_server* s, int32_t mesh_id);
+/* Validates and queues a request; DM_ERR_BUSY if the queue is full. */
+dm_status dm_submit(dm_server* s, const dm_serve_request* r, uint64_t* ticket);
+/* DM_ERR_BUSY (non-blocking) while the request is not finished; once it has
+ * finished, fills `out` and forgets the ticket (DM_ERR_STATE afterwards). */
+dm_status dm_poll(dm_server* s, uint64_t ticket, int blocking, dm_serve_result* out);
+dm_status dm_server_stats_read(dm_server* s, dm_server_stats* out);
+
 /* ------------------------------------------------------------ diagnostics */
 
 /* Kernel timing: while enabled, the handle records HIP events on the call's
  * stream around every launch of the two mesh-transform sweeps (the forward
- * sweep of Eq. 5/7-8 and the gradient sweep of Eq. 6/9-10).  dm_timing_read
- * waits for those events and returns, per sweep kind, the number of launches,
+ * sweep of Eq. 5/7-8 and the gradient sweep of Eq. 6/9-10) and of the batched
+ * sweep of dm_batch_run.  dm_timing_read waits for those events and returns,
+ * per sweep kind, the number of launches,
  * the summed duration in milliseconds and the summed frequency-triangle
  * pairs they evaluated; reset != 0 clears the counters.  Any output may be
  * NULL. */
@@ -194,7 +285,8 @@ typedef struct {
 } dm_kernel_time;
 
 dm_status dm_timing_enable(dm_handle* h, int enable);
-dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time* vjp_sweep, int reset);
+dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time* vjp_sweep,
+                         dm_kernel_time* batch_sweep, int reset);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* dm_last_error(void);

@@ -56,6 +56,31 @@ class CMesh(ctypes.Structure):
     _fields_ = [("verts_dev", ctypes.c_void_p), ("n_verts", ctypes.c_int32), ("topo", ctypes.c_void_p)]
 
 
+class CServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class CServeRequest(ctypes.Structure):
+    _fields_ = [("mesh_id", ctypes.c_int32), ("psf", CPsf), ("grid", CGrid), ("dL_dimage_dev", ctypes.c_void_p),
+                ("image_dev", ctypes.c_void_p), ("dL_dverts_dev", ctypes.c_void_p), ("dL_dsigma_dev", ctypes.c_void_p)]
+
+
+class CServeResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("batch_size", ctypes.c_int32), ("queue_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class CServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("peak_inflight_bytes", ctypes.c_size_t)]
+
+
+class CRequest(ctypes.Structure):
+    _fields_ = [("mesh", CMesh), ("psf", CPsf), ("grid", CGrid), ("dL_dimage_dev", ctypes.c_void_p),
+                ("image_dev", ctypes.c_void_p), ("dL_dverts_dev", ctypes.c_void_p), ("dL_dsigma_dev", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -82,7 +107,16 @@ def _load():
                           vp, vp],
         "dm_mesh_transform": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CGrid), vp, i64, vp, vp],
         "dm_timing_enable": [vp, ctypes.c_int],
-        "dm_timing_read": [vp, ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime), ctypes.c_int],
+        "dm_timing_read": [vp, ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime),
+                           ctypes.c_int],
+        "dm_batch_run": [vp, i32, vp, vp],
+        "dm_server_create": [ctypes.c_int, ctypes.POINTER(CServerConfig), ctypes.POINTER(vp)],
+        "dm_server_destroy": [vp],
+        "dm_server_mesh_add": [vp, vp, i32, vp, i32, ctypes.POINTER(i32)],
+        "dm_server_mesh_remove": [vp, i32],
+        "dm_submit": [vp, ctypes.POINTER(CServeRequest), ctypes.POINTER(ctypes.c_uint64)],
+        "dm_poll": [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(CServeResult)],
+        "dm_server_stats_read": [vp, ctypes.POINTER(CServerStats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -193,11 +227,12 @@ class Handle:
     def timing_read(self, reset: bool = True) -> dict:
         """{'fwd': (launches, ms, pairs), 'vjp': (...)} from the HIP events the
         library records around each sweep launch."""
-        a, b = CKernelTime(), CKernelTime()
-        _check(_load().dm_timing_read(self._h, ctypes.byref(a), ctypes.byref(b), 1 if reset else 0),
+        a, b, c = CKernelTime(), CKernelTime(), CKernelTime()
+        _check(_load().dm_timing_read(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 1 if reset else 0),
                "dm_timing_read")
         return {"fwd": (int(a.launches), float(a.ms), float(a.pairs)),
-                "vjp": (int(b.launches), float(b.ms), float(b.pairs))}
+                "vjp": (int(b.launches), float(b.ms), float(b.pairs)),
+                "batch": (int(c.launches), float(c.ms), float(c.pairs))}
 
     def topology(self, faces, n_verts: int | None = None) -> "Topology":
         return Topology(self, faces, n_verts)
@@ -312,6 +347,101 @@ def render_vjp(h: Handle, verts, topo: Topology, sigma6, grid, dL_dimage, want_v
     _check(_load().dm_render_vjp(h.ptr, ctypes.byref(m), ctypes.byref(p), ctypes.byref(g), ptr(gI), ptr(dv), ptr(ds),
                                  ptr(img), ptr(sp), _stream(h.device)), "dm_render_vjp")
     return dv, ds, img
+
+
+def batch_run(h: Handle, requests, want_image: bool = True, want_verts: bool = True, want_sigma: bool = True):
+    """Runs many independent requests as one batch (dm_batch_run).
+
+    ``requests``: sequence of (verts, topo, sigma6, grid, dL_dimage or None).
+    Returns a list of (image | None, dL/dverts | None, dL/dsigma | None)."""
+    torch = _torch()
+    n = len(requests)
+    arr = (CRequest * max(n, 1))()
+    outs, keep = [], []
+    for i, (verts, topo, sigma6, grid, gI) in enumerate(requests):
+        verts = _dev_tensor(verts, torch.float32, 3, "verts")
+        shape = tuple(int(x) for x in grid.n)
+        if gI is not None:
+            gI = _dev_tensor(gI, torch.float32, None, "dL_dimage")
+            if tuple(gI.shape) != shape:
+                raise ValueError("dL_dimage must have the grid's shape")
+        img = torch.empty(shape, dtype=torch.float32, device=verts.device) if want_image else None
+        dv = torch.empty_like(verts) if (want_verts and gI is not None) else None
+        ds = torch.empty(6, dtype=torch.float32, device=verts.device) if (want_sigma and gI is not None) else None
+        r = arr[i]
+        r.mesh = _mesh(verts, topo)
+        r.psf = _psf(sigma6)
+        r.grid = _grid(grid)
+        r.dL_dimage_dev = gI.data_ptr() if gI is not None else None
+        r.image_dev = img.data_ptr() if img is not None else None
+        r.dL_dverts_dev = dv.data_ptr() if dv is not None else None
+        r.dL_dsigma_dev = ds.data_ptr() if ds is not None else None
+        outs.append((img, dv, ds))
+        keep.append((verts, gI))
+    _check(_load().dm_batch_run(h.ptr, n, ctypes.cast(arr, ctypes.c_void_p), _stream(h.device)), "dm_batch_run")
+    return outs
+
+
+class Server:
+    """Continuous-batching server (dm_server_*): resident meshes, submit/poll."""
+
+    def __init__(self, device: int = 0, max_batch: int = 32, max_inflight: int = 2, queue_capacity: int = 100000,
+                 hbm_budget_bytes: int = 0):
+        L = _load()
+        cfg = CServerConfig(int(max_batch), int(max_inflight), int(queue_capacity), int(hbm_budget_bytes))
+        self.device = int(device)
+        self._s = ctypes.c_void_p()
+        _check(L.dm_server_create(self.device, ctypes.byref(cfg), ctypes.byref(self._s)), "dm_server_create")
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            _load().dm_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mesh_add(self, V, F) -> int:
+        V = np.ascontiguousarray(np.asarray(V, dtype=np.float32))
+        F = np.ascontiguousarray(np.asarray(F, dtype=np.int32))
+        mid = ctypes.c_int32()
+        _check(_load().dm_server_mesh_add(self._s, ctypes.c_void_p(V.ctypes.data), V.shape[0],
+                                          ctypes.c_void_p(F.ctypes.data), F.shape[0], ctypes.byref(mid)),
+               "dm_server_mesh_add")
+        return int(mid.value)
+
+    def mesh_remove(self, mesh_id: int):
+        _check(_load().dm_server_mesh_remove(self._s, int(mesh_id)), "dm_server_mesh_remove")
+
+    def submit(self, mesh_id: int, sigma6, grid, dL_dimage=None, image=None, dverts=None, dsigma=None) -> int:
+        """Queues a request; the tensors must stay alive until poll() reports it."""
+        r = CServeRequest()
+        r.mesh_id = int(mesh_id)
+        r.psf = _psf(sigma6)
+        r.grid = _grid(grid)
+        p = lambda t: t.data_ptr() if t is not None else None
+        r.dL_dimage_dev, r.image_dev, r.dL_dverts_dev, r.dL_dsigma_dev = p(dL_dimage), p(image), p(dverts), p(dsigma)
+        t = ctypes.c_uint64()
+        _check(_load().dm_submit(self._s, ctypes.byref(r), ctypes.byref(t)), "dm_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int, blocking: bool = True):
+        """None while pending; else {'status', 'batch_size', 'queue_ms', 'total_ms'}."""
+        res = CServeResult()
+        st = _load().dm_poll(self._s, ctypes.c_uint64(ticket), 1 if blocking else 0, ctypes.byref(res))
+        if st == -7:
+            return None
+        _check(st, "dm_poll")
+        return {"status": int(res.status), "batch_size": int(res.batch_size), "queue_ms": float(res.queue_ms),
+                "total_ms": float(res.total_ms)}
+
+    def stats(self) -> dict:
+        st = CServerStats()
+        _check(_load().dm_server_stats_read(self._s, ctypes.byref(st)), "dm_server_stats_read")
+        return {k: getattr(st, k) for k, _ in CServerStats._fields_}
 
 
 def mesh_transform(h: Handle, verts, topo: Topology, grid, k):

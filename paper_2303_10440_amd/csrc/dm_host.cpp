@@ -5,7 +5,12 @@
 #include <rocfft/rocfft.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -85,6 +90,7 @@ struct BandEntry {
   BandDev dev{};
   void* mem = nullptr;
   size_t bytes = 0;
+  int pins = 0;   // > 0 while a batch being enqueued uses this band
 };
 
 struct FftPlans {
@@ -95,7 +101,7 @@ struct FftPlans {
 // Event pairs recorded around sweep launches while timing is enabled.
 struct TimedLaunch {
   hipEvent_t a = nullptr, b = nullptr;
-  int kind = 0;   // 0 forward sweep, 1 gradient sweep
+  int kind = 0;   // 0 forward sweep, 1 gradient sweep, 2 batched sweep
   double pairs = 0.0;
 };
 
@@ -118,7 +124,7 @@ struct dm_handle {
   bool timing = false;
   std::vector<TimedLaunch> pending;   // recorded, not yet read
   std::vector<hipEvent_t> event_pool;
-  dm_kernel_time acc[2] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}};
+  dm_kernel_time acc[3] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}, {0, 0.0, 0.0}};
 };
 
 struct dm_topology {
@@ -149,22 +155,26 @@ void dev_free(dm_handle* h, void* p, size_t bytes) {
   h->in_use -= std::min(h->in_use, bytes);
 }
 
-void evict_one_band(dm_handle* h) {
-  if (h->band_lru.empty()) return;
-  BandKey k = h->band_lru.back();
-  h->band_lru.pop_back();
-  auto it = h->bands.find(k);
-  if (it != h->bands.end()) {
+// Frees the least recently used band that no batch in preparation holds.
+// Returns false if every cached band is pinned.
+bool evict_one_band(dm_handle* h) {
+  for (auto lit = h->band_lru.rbegin(); lit != h->band_lru.rend(); ++lit) {
+    auto it = h->bands.find(*lit);
+    if (it == h->bands.end() || it->second.pins > 0) continue;
     (void)hipDeviceSynchronize();
     dev_free(h, it->second.mem, it->second.bytes);
     h->bands.erase(it);
+    h->band_lru.erase(std::next(lit).base());
+    return true;
   }
+  return false;
 }
 
 // Workspace: one growable device buffer carved per call.
 dm_status ensure_ws(dm_handle* h, size_t bytes) {
   if (bytes <= h->ws_bytes) return DM_OK;
-  while (h->budget && h->in_use - h->ws_bytes + bytes > h->budget && !h->band_lru.empty()) evict_one_band(h);
+  while (h->budget && h->in_use - h->ws_bytes + bytes > h->budget && evict_one_band(h)) {
+  }
   if (h->ws) {
     HIP_TRY(hipDeviceSynchronize());
     dev_free(h, h->ws, h->ws_bytes);
@@ -260,12 +270,13 @@ double band_qmax(float tau) {
 }
 
 // Builds (or fetches) the band for (grid, psf).  Synchronises `s` on a miss.
-dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t s, BandDev* out) {
+dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t s, BandDev* out, bool pin = false) {
   const BandKey key = make_key(g, p);
   auto it = h->bands.find(key);
   if (it != h->bands.end()) {
     h->band_lru.remove(key);
     h->band_lru.push_front(key);
+    if (pin) it->second.pins++;
     *out = it->second.dev;
     return DM_OK;
   }
@@ -293,7 +304,8 @@ dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t 
   const int64_t ne = std::max<int64_t>(total, 1);
   const size_t o_kf = bc.take<float4>(ne), o_w = bc.take<float>(ne), o_pos = bc.take<int32_t>(ne),
                o_map = bc.take<int32_t>(n_pos);
-  while (h->budget && h->in_use + bc.off > h->budget && !h->band_lru.empty()) evict_one_band(h);
+  while (h->budget && h->in_use + bc.off > h->budget && evict_one_band(h)) {
+  }
   BandEntry be;
   DM_TRY(dev_alloc(h, &be.mem, bc.off));
   be.bytes = bc.off;
@@ -310,10 +322,16 @@ dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t 
     dev_free(h, be.mem, be.bytes);
     return fail(DM_ERR_DEVICE, "band fill: %s", hipGetErrorString(e));
   }
+  be.pins = pin ? 1 : 0;
   h->bands[key] = be;
   h->band_lru.push_front(key);
   *out = be.dev;
   return DM_OK;
+}
+
+void unpin_band(dm_handle* h, const dm_grid* g, const dm_psf* p) {
+  auto it = h->bands.find(make_key(g, p));
+  if (it != h->bands.end() && it->second.pins > 0) it->second.pins--;
 }
 
 dm_status get_fft(dm_handle* h, const dm_grid* g, FftPlans** out) {
@@ -439,6 +457,304 @@ dm_status zero_fill(float* p, int64_t n, hipStream_t s) {
   return DM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// One render / gradient request, split into stages so that a single call and
+// a batch of many requests share everything except the sweep launch.
+struct ReqPlan {
+  const dm_mesh* m = nullptr;
+  dm_grid g{};
+  dm_psf psf{};
+  const float* dLdI = nullptr;
+  float* image = nullptr;
+  float* dV = nullptr;
+  float* dS = nullptr;
+  const float* spec_in = nullptr;
+  float* spec_out = nullptr;
+  int mode = 0, nt = 0, nv = 0, nc = 3, prep_blocks = 1, adj_blocks = 1;
+  int64_t nvox = 0, nE = 0;
+  bool want_vjp = false, need_spec = false, empty = false, pinned = false;
+  GridC gc{};
+  BandDev b{};
+  FftPlans* fp = nullptr;
+  SweepPlan fsp, vsp;
+  size_t o_rec = 0, o_info = 0, o_ptmp = 0, o_part = 0, o_spec = 0, o_x = 0, o_fftw = 0, o_gin = 0, o_ghat = 0,
+         o_erec = 0, o_dsp = 0, o_vpart = 0, o_red = 0, o_rtmp = 0, o_R = 0, bytes = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* ptr(size_t off) const {
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// Batch chunking depends on the request alone, so a request's result is the
+// same whichever other requests share its batch.
+SweepPlan plan_fwd_batch(int64_t nE, int nt) {
+  SweepPlan sp;
+  (void)nE;
+  sp.per_chunk = std::max(1, std::min(nt, 640));
+  sp.n_chunks = (nt + sp.per_chunk - 1) / sp.per_chunk;
+  return sp;
+}
+
+SweepPlan plan_vjp_batch(int64_t nE, int nt) {
+  SweepPlan sp;
+  (void)nt;
+  sp.per_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nE, 1024));
+  sp.n_chunks = (int)((nE + sp.per_chunk - 1) / sp.per_chunk);
+  return sp;
+}
+
+dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch) {
+  P.mode = P.g.mode;
+  P.gc = make_gridc(&P.g);
+  P.nt = P.m->topo->nt;
+  P.nv = P.m->n_verts;
+  P.nvox = (int64_t)P.g.n[0] * P.g.n[1] * P.g.n[2];
+  P.want_vjp = P.dLdI && (P.dV || P.dS);
+  DM_TRY(get_band(h, &P.g, &P.psf, s, &P.b, batch));
+  P.pinned = batch;
+  P.nE = P.b.n_entries;
+  if (P.image || P.want_vjp) DM_TRY(get_fft(h, &P.g, &P.fp));
+  P.empty = P.nE == 0 || P.nt == 0;
+  P.need_spec = (P.image && !P.spec_in) || (P.dS && !P.spec_in) || P.spec_out;
+  P.fsp = batch ? plan_fwd_batch(P.nE, P.nt) : plan_fwd(P.nE, P.nt);
+  P.vsp = batch ? plan_vjp_batch(P.nE, P.nt) : plan_vjp(P.nE, P.nt);
+  P.nc = nchannels(P.mode);
+  P.prep_blocks = mesh_prep_blocks(P.nt);
+  P.adj_blocks = adjoint_blocks(P.gc);
+  Carver cv;
+  if (!P.empty) {
+    const bool vjp_v = P.want_vjp && P.dV;
+    P.o_rec = cv.take<float>((size_t)P.nt * TRI_REC);
+    P.o_info = cv.take<MeshInfo>(1);
+    P.o_ptmp = cv.take<double>(2 * (size_t)P.prep_blocks);
+    P.o_part = P.need_spec ? cv.take<float2>((size_t)P.fsp.n_chunks * P.nE) : 0;
+    P.o_spec = (P.need_spec && !P.spec_out) ? cv.take<float2>(P.nE) : 0;
+    P.o_x = P.image ? cv.take<float2>(P.b.n_pos) : 0;
+    P.o_fftw = cv.take<char>(P.fp ? std::max(P.fp->work_c2r, P.fp->work_r2c) : 0);
+    P.o_gin = P.want_vjp ? cv.take<float>(P.nvox) : 0;
+    P.o_ghat = P.want_vjp ? cv.take<float2>(P.b.n_pos) : 0;
+    P.o_erec = vjp_v ? cv.take<float4>(2 * (size_t)P.nE) : 0;
+    P.o_dsp = (P.want_vjp && P.dS) ? cv.take<double>(6 * (size_t)P.adj_blocks) : 0;
+    P.o_vpart = vjp_v ? cv.take<float>((size_t)P.vsp.n_chunks * P.nc * P.nt) : 0;
+    P.o_red = vjp_v ? cv.take<float>((size_t)P.nc * P.nt) : 0;
+    P.o_rtmp = vjp_v ? cv.take<float>((size_t)vjp_reduce_groups(P.vsp.n_chunks) * P.nc * P.nt) : 0;
+    P.o_R = cv.take<double>(1);
+  }
+  P.bytes = cv.off;
+  return DM_OK;
+}
+
+const float2* spectrum_of(const ReqPlan& P) {
+  if (P.need_spec) return P.spec_out ? reinterpret_cast<const float2*>(P.spec_out) : P.ptr<float2>(P.o_spec);
+  return reinterpret_cast<const float2*>(P.spec_in);
+}
+
+// Mesh prep and, for the gradient, FFT of dL/dI and adjoint weights.
+dm_status stage_pre(dm_handle* h, ReqPlan& P, hipStream_t s) {
+  if (P.empty) {
+    DM_TRY(zero_fill(P.image, P.nvox, s));
+    DM_TRY(zero_fill(P.spec_out, 2 * P.nE, s));
+    DM_TRY(zero_fill(P.dV, 3 * (int64_t)P.nv, s));
+    DM_TRY(zero_fill(P.dS, 6, s));
+    return DM_OK;
+  }
+  HIP_TRY(launch_mesh_prep(P.mode, P.gc, P.m->verts_dev, P.nv, P.m->topo->faces, P.nt, P.ptr<float>(P.o_rec),
+                           P.ptr<MeshInfo>(P.o_info), P.ptr<double>(P.o_ptmp), P.prep_blocks, s));
+  if (P.want_vjp) {
+    HIP_TRY(hipMemcpyAsync(P.ptr<float>(P.o_gin), P.dLdI, (size_t)P.nvox * sizeof(float), hipMemcpyDeviceToDevice, s));
+    DM_TRY(run_fft(h, P.fp->r2c, P.ptr<float>(P.o_gin), P.ptr<float2>(P.o_ghat), P.ptr<char>(P.o_fftw),
+                   P.fp->work_r2c, s));
+    if (P.dV)
+      HIP_TRY(launch_adjoint(P.mode, P.gc, P.b, P.ptr<float2>(P.o_ghat), P.ptr<MeshInfo>(P.o_info),
+                             P.ptr<float4>(P.o_erec), s));
+  }
+  return DM_OK;
+}
+
+// The two sweeps as separate launches (single-request path).
+dm_status stage_sweeps(dm_handle* h, ReqPlan& P, hipStream_t s) {
+  if (P.empty) return DM_OK;
+  if (P.need_spec) {
+    SweepTimer tm(h, s, 0, (double)P.nE * P.nt);
+    HIP_TRY(launch_fwd_sweep(P.mode, P.b.kf, P.nE, P.ptr<float>(P.o_rec), P.nt, P.fsp.per_chunk, P.fsp.n_chunks,
+                             P.ptr<float2>(P.o_part), s));
+    tm.done();
+  }
+  if (P.want_vjp && P.dV) {
+    SweepTimer tm(h, s, 1, (double)P.nE * P.nt);
+    HIP_TRY(launch_vjp_sweep(P.mode, P.ptr<float>(P.o_rec), P.nt, P.ptr<float4>(P.o_erec), P.nE, P.vsp.per_chunk,
+                             P.vsp.n_chunks, P.ptr<float>(P.o_vpart), s));
+    tm.done();
+  }
+  return DM_OK;
+}
+
+// Work items of this request for the persistent batched sweep.
+void add_items(const ReqPlan& P, int req, std::vector<SweepItem>& items, std::vector<double>& cost) {
+  if (P.empty) return;
+  if (P.need_spec)
+    for (int c = 0; c < P.fsp.n_chunks; ++c) {
+      const int tris = std::min(P.nt, (c + 1) * P.fsp.per_chunk) - c * P.fsp.per_chunk;
+      for (int64_t x0 = 0; x0 < P.nE; x0 += SWEEP_THREADS) {
+        items.push_back({0, req, (int)x0, c});
+        cost.push_back((double)tris * (double)std::min<int64_t>(SWEEP_THREADS, P.nE - x0));
+      }
+    }
+  if (P.want_vjp && P.dV)
+    for (int c = 0; c < P.vsp.n_chunks; ++c) {
+      const int64_t ents = std::min<int64_t>(P.nE, (int64_t)(c + 1) * P.vsp.per_chunk) - (int64_t)c * P.vsp.per_chunk;
+      for (int x0 = 0; x0 < P.nt; x0 += SWEEP_THREADS) {
+        items.push_back({1, req, x0, c});
+        cost.push_back(1.9 * (double)ents * (double)std::min(SWEEP_THREADS, P.nt - x0));
+      }
+    }
+}
+
+SweepReq sweep_req(const ReqPlan& P) {
+  SweepReq q{};
+  q.mode = P.mode;
+  q.nE = (int)P.nE;
+  q.nt = P.nt;
+  q.tpc = P.fsp.per_chunk;
+  q.epc = P.vsp.per_chunk;
+  q.kf = P.b.kf;
+  q.rec = P.empty ? nullptr : P.ptr<float>(P.o_rec);
+  q.fpart = P.need_spec && !P.empty ? P.ptr<float2>(P.o_part) : nullptr;
+  q.erec = P.want_vjp && P.dV && !P.empty ? P.ptr<float4>(P.o_erec) : nullptr;
+  q.vpart = P.want_vjp && P.dV && !P.empty ? P.ptr<float>(P.o_vpart) : nullptr;
+  return q;
+}
+
+// Spectrum, image, PSF gradient and vertex gradient from the sweep partials.
+dm_status stage_post(dm_handle* h, ReqPlan& P, hipStream_t s) {
+  if (P.empty) return DM_OK;
+  MeshInfo* info = P.ptr<MeshInfo>(P.o_info);
+  float2* xh = P.image ? P.ptr<float2>(P.o_x) : nullptr;
+  if (P.need_spec) {
+    float2* sp = P.spec_out ? reinterpret_cast<float2*>(P.spec_out) : P.ptr<float2>(P.o_spec);
+    HIP_TRY(launch_fwd_finalize(P.mode, P.gc, P.b, P.ptr<float2>(P.o_part), P.fsp.n_chunks, info, sp, xh, s));
+  } else if (P.image) {
+    HIP_TRY(launch_spec_scatter(P.gc, P.b, reinterpret_cast<const float2*>(P.spec_in), xh, s));
+  }
+  if (P.image) DM_TRY(run_fft(h, P.fp->c2r, xh, P.image, P.ptr<char>(P.o_fftw), P.fp->work_c2r, s));
+  if (P.want_vjp && P.dS) {
+    double* dsp = P.ptr<double>(P.o_dsp);
+    HIP_TRY(launch_dsig(P.gc, P.b, P.ptr<float2>(P.o_ghat), spectrum_of(P), dsp, P.adj_blocks, s));
+    HIP_TRY(launch_dsig_final(dsp, P.adj_blocks, P.dS, s));
+  }
+  if (P.want_vjp && P.dV) {
+    float* red = P.ptr<float>(P.o_red);
+    HIP_TRY(launch_vjp_reduce(P.mode, P.ptr<float>(P.o_vpart), P.vsp.n_chunks, P.nt, P.ptr<float>(P.o_rtmp), red, s));
+    double* R = P.ptr<double>(P.o_R);
+    if (P.mode == DM_SURFACE) HIP_TRY(launch_surface_scalar(red, P.ptr<float>(P.o_rec), P.nt, info, R, s));
+    HIP_TRY(launch_vertex_gather(P.mode, P.m->verts_dev, P.nv, P.m->topo->faces, P.nt, P.m->topo->csr_off,
+                                 P.m->topo->csr_ent, red, R, P.dV, s));
+  }
+  return DM_OK;
+}
+
+dm_status render_impl(dm_handle* h, const dm_mesh* m, const dm_psf* psf, const dm_grid* g, float* image,
+                      float* spec_out, const float* dLdI, float* dV, float* dS, const float* spec_in, hipStream_t s) {
+  DM_TRY(begin_call(h, s));
+  ReqPlan P;
+  P.m = m;
+  P.g = *g;
+  P.psf = *psf;
+  P.image = image;
+  P.spec_out = spec_out;
+  P.dLdI = dLdI;
+  P.dV = dV;
+  P.dS = dS;
+  P.spec_in = spec_in;
+  DM_TRY(plan_request(h, P, s, false));
+  DM_TRY(ensure_ws(h, P.bytes));
+  P.base = static_cast<char*>(h->ws);
+  DM_TRY(stage_pre(h, P, s));
+  DM_TRY(stage_sweeps(h, P, s));
+  DM_TRY(stage_post(h, P, s));
+  return end_call(h, s);
+}
+
+dm_status check_request(const dm_request& r, int i) {
+  DM_TRY(check_grid(&r.grid));
+  DM_TRY(check_psf(&r.psf));
+  DM_TRY(check_mesh(&r.mesh, r.grid.mode));
+  if (!r.image_dev && !r.dL_dverts_dev && !r.dL_dsigma_dev) return fail(DM_ERR_ARG, "request %d: no output", i);
+  if ((r.dL_dverts_dev || r.dL_dsigma_dev) && !r.dL_dimage_dev)
+    return fail(DM_ERR_ARG, "request %d: gradients need dL_dimage", i);
+  return DM_OK;
+}
+
+void fill_plan(ReqPlan& P, const dm_request& r) {
+  P.m = &r.mesh;
+  P.g = r.grid;
+  P.psf = r.psf;
+  P.dLdI = r.dL_dimage_dev;
+  P.image = r.image_dev;
+  P.dV = r.dL_dimage_dev ? r.dL_dverts_dev : nullptr;
+  P.dS = r.dL_dimage_dev ? r.dL_dsigma_dev : nullptr;
+}
+
+// Device layout of a batch: request regions, then the sorted work list, the
+// per-request sweep descriptors and the queue counter.
+struct BatchLayout {
+  std::vector<size_t> off;
+  std::vector<SweepItem> items;   // longest first
+  std::vector<SweepReq> reqs;
+  size_t o_items = 0, o_reqs = 0, o_counter = 0, total = 0;
+  double pairs = 0.0;
+};
+
+void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
+  const size_t n = P.size();
+  std::vector<SweepItem> items;
+  std::vector<double> cost;
+  L.off.assign(n, 0);
+  L.total = 0;
+  L.pairs = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    L.off[i] = L.total;
+    L.total += align_up(P[i].bytes);
+    add_items(P[i], (int)i, items, cost);
+    L.pairs += (double)P[i].nE * P[i].nt;
+  }
+  std::vector<size_t> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  L.items.resize(items.size());
+  for (size_t i = 0; i < order.size(); ++i) L.items[i] = items[order[i]];
+  L.o_items = L.total;
+  L.total += align_up(std::max<size_t>(1, L.items.size()) * sizeof(SweepItem));
+  L.o_reqs = L.total;
+  L.total += align_up(std::max<size_t>(1, n) * sizeof(SweepReq));
+  L.o_counter = L.total;
+  L.total += 256;
+}
+
+dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s) {
+  const size_t n = P.size();
+  L.reqs.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    P[i].base = base + L.off[i];
+    L.reqs[i] = sweep_req(P[i]);
+  }
+  for (size_t i = 0; i < n; ++i) DM_TRY(stage_pre(h, P[i], s));
+  if (!L.items.empty()) {
+    HIP_TRY(hipMemcpyAsync(base + L.o_items, L.items.data(), L.items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
+                           s));
+    HIP_TRY(hipMemcpyAsync(base + L.o_reqs, L.reqs.data(), n * sizeof(SweepReq), hipMemcpyHostToDevice, s));
+    const int blocks = (int)std::min<size_t>(L.items.size(), 2048);
+    SweepTimer tm(h, s, 2, L.pairs);
+    HIP_TRY(launch_batch_sweep(reinterpret_cast<const SweepItem*>(base + L.o_items), (int)L.items.size(),
+                               reinterpret_cast<const SweepReq*>(base + L.o_reqs),
+                               reinterpret_cast<int*>(base + L.o_counter), blocks, s));
+    tm.done();
+  }
+  for (size_t i = 0; i < n; ++i) DM_TRY(stage_post(h, P[i], s));
+  return DM_OK;
+}
+
 }  // namespace
 
 // =================================================================== ABI
@@ -497,7 +813,8 @@ dm_status dm_timing_enable(dm_handle* h, int enable) {
   return DM_OK;
 }
 
-dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time* vjp_sweep, int reset) {
+dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time* vjp_sweep,
+                         dm_kernel_time* batch_sweep, int reset) {
   g_err.clear();
   if (!h) return fail(DM_ERR_ARG, "NULL handle");
   DeviceGuard dg(h->device);
@@ -514,7 +831,8 @@ dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time
   h->pending.clear();
   if (fwd_sweep) *fwd_sweep = h->acc[0];
   if (vjp_sweep) *vjp_sweep = h->acc[1];
-  if (reset) h->acc[0] = h->acc[1] = dm_kernel_time{0, 0.0, 0.0};
+  if (batch_sweep) *batch_sweep = h->acc[2];
+  if (reset) h->acc[0] = h->acc[1] = h->acc[2] = dm_kernel_time{0, 0.0, 0.0};
   return DM_OK;
 }
 
@@ -660,99 +978,6 @@ dm_status dm_band_export(dm_handle* h, const dm_grid* g, const dm_psf* psf, int3
   return DM_OK;
 }
 
-// The forward and backward passes share one implementation.
-static dm_status render_impl(dm_handle* h, const dm_mesh* m, const dm_psf* psf, const dm_grid* g, float* image,
-                             float* spec_out, const float* dLdI, float* dV, float* dS, const float* spec_in,
-                             hipStream_t s) {
-  const int mode = g->mode;
-  const GridC gc = make_gridc(g);
-  const int nt = m->topo->nt, nv = m->n_verts;
-  const int64_t nvox = (int64_t)g->n[0] * g->n[1] * g->n[2];
-  const bool want_vjp = dLdI && (dV || dS);
-  DM_TRY(begin_call(h, s));
-  BandDev b;
-  DM_TRY(get_band(h, g, psf, s, &b));
-  const int64_t nE = b.n_entries;
-  FftPlans* fp = nullptr;
-  if (image || want_vjp) DM_TRY(get_fft(h, g, &fp));
-
-  // Empty band or empty mesh: zero outputs.
-  if (nE == 0 || nt == 0) {
-    DM_TRY(zero_fill(image, nvox, s));
-    DM_TRY(zero_fill(spec_out, 2 * nE, s));
-    DM_TRY(zero_fill(dV, 3 * (int64_t)nv, s));
-    DM_TRY(zero_fill(dS, 6, s));
-    return end_call(h, s);
-  }
-
-  const bool need_spec = (image && !spec_in) || (dS && !spec_in) || spec_out;
-  const SweepPlan fsp = plan_fwd(nE, nt);
-  const SweepPlan vsp = plan_vjp(nE, nt);
-  const int nc = nchannels(mode);
-  const int prep_blocks = mesh_prep_blocks(nt);
-  const int adj_blocks = adjoint_blocks(gc);
-  Carver cv;
-  const size_t o_rec = cv.take<float>((size_t)nt * TRI_REC);
-  const size_t o_info = cv.take<MeshInfo>(1);
-  const size_t o_ptmp = cv.take<double>(2 * (size_t)prep_blocks);
-  const size_t o_part = need_spec ? cv.take<float2>((size_t)fsp.n_chunks * nE) : 0;
-  const size_t o_spec = (need_spec && !spec_out) ? cv.take<float2>(nE) : 0;
-  const size_t o_x = image ? cv.take<float2>(b.n_pos) : 0;
-  const size_t o_fftw = cv.take<char>(fp ? std::max(fp->work_c2r, fp->work_r2c) : 0);
-  const size_t o_gin = want_vjp ? cv.take<float>(nvox) : 0;
-  const size_t o_ghat = want_vjp ? cv.take<float2>(b.n_pos) : 0;
-  const size_t o_erec = want_vjp ? cv.take<float4>(2 * (size_t)nE) : 0;
-  const size_t o_dsp = (want_vjp && dS) ? cv.take<double>(6 * (size_t)adj_blocks) : 0;
-  const size_t o_vpart = (want_vjp && dV) ? cv.take<float>((size_t)vsp.n_chunks * nc * nt) : 0;
-  const size_t o_red = (want_vjp && dV) ? cv.take<float>((size_t)nc * nt) : 0;
-  const size_t o_R = cv.take<double>(1);
-  DM_TRY(ensure_ws(h, cv.off));
-
-  float* rec = at<float>(h, o_rec);
-  MeshInfo* info = at<MeshInfo>(h, o_info);
-  HIP_TRY(launch_mesh_prep(mode, gc, m->verts_dev, nv, m->topo->faces, nt, rec, info, at<double>(h, o_ptmp),
-                           prep_blocks, s));
-
-  const float2* spec = reinterpret_cast<const float2*>(spec_in);
-  if (need_spec) {
-    float2* part = at<float2>(h, o_part);
-    float2* sp = spec_out ? reinterpret_cast<float2*>(spec_out) : at<float2>(h, o_spec);
-    SweepTimer tm(h, s, 0, (double)nE * nt);
-    HIP_TRY(launch_fwd_sweep(mode, b.kf, nE, rec, nt, fsp.per_chunk, fsp.n_chunks, part, s));
-    tm.done();
-    float2* xh = image ? at<float2>(h, o_x) : nullptr;
-    HIP_TRY(launch_fwd_finalize(mode, gc, b, part, fsp.n_chunks, info, sp, xh, s));
-    spec = sp;
-  } else if (image) {
-    HIP_TRY(launch_spec_scatter(gc, b, spec, at<float2>(h, o_x), s));
-  }
-  if (image)
-    DM_TRY(run_fft(h, fp->c2r, at<float2>(h, o_x), image, at<char>(h, o_fftw), fp->work_c2r, s));
-
-  if (want_vjp) {
-    float* gin = at<float>(h, o_gin);
-    HIP_TRY(hipMemcpyAsync(gin, dLdI, (size_t)nvox * sizeof(float), hipMemcpyDeviceToDevice, s));
-    float2* ghat = at<float2>(h, o_ghat);
-    DM_TRY(run_fft(h, fp->r2c, gin, ghat, at<char>(h, o_fftw), fp->work_r2c, s));
-    float4* erec = at<float4>(h, o_erec);
-    double* dsp = dS ? at<double>(h, o_dsp) : nullptr;
-    HIP_TRY(launch_adjoint(mode, gc, b, ghat, info, dS ? spec : nullptr, erec, dsp, adj_blocks, s));
-    if (dS) HIP_TRY(launch_dsig_final(dsp, adj_blocks, dS, s));
-    if (dV) {
-      float* vpart = at<float>(h, o_vpart);
-      float* red = at<float>(h, o_red);
-      SweepTimer tm(h, s, 1, (double)nE * nt);
-      HIP_TRY(launch_vjp_sweep(mode, rec, nt, erec, nE, vsp.per_chunk, vsp.n_chunks, vpart, s));
-      tm.done();
-      HIP_TRY(launch_vjp_reduce(mode, vpart, vsp.n_chunks, nt, red, s));
-      double* R = at<double>(h, o_R);
-      if (mode == DM_SURFACE) HIP_TRY(launch_surface_scalar(red, rec, nt, info, R, s));
-      HIP_TRY(launch_vertex_gather(mode, m->verts_dev, nv, m->topo->faces, nt, m->topo->csr_off, m->topo->csr_ent, red,
-                                   R, dV, s));
-    }
-  }
-  return end_call(h, s);
-}
 
 dm_status dm_render(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, const dm_grid* g, float* image_dev,
                     float* spectrum_dev, void* stream) {
@@ -780,6 +1005,34 @@ dm_status dm_render_vjp(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, co
   DeviceGuard dg(h->device);
   return render_impl(h, mesh, psf, g, image_dev, nullptr, dL_dimage_dev, dL_dverts_dev, dL_dsigma_dev,
                      spectrum_in_dev, (hipStream_t)stream);
+}
+
+dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* stream) {
+  g_err.clear();
+  if (!h) return fail(DM_ERR_ARG, "NULL handle");
+  if (n < 0 || (n > 0 && !reqs)) return fail(DM_ERR_ARG, "bad request list");
+  for (int i = 0; i < n; ++i) DM_TRY(check_request(reqs[i], i));
+  if (n == 0) return DM_OK;
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  DM_TRY(begin_call(h, s));
+  std::vector<ReqPlan> P((size_t)n);
+  int planned = 0;
+  dm_status st = DM_OK;
+  for (int i = 0; i < n && st == DM_OK; ++i) {
+    fill_plan(P[i], reqs[i]);
+    st = plan_request(h, P[i], s, true);
+    if (st == DM_OK) planned = i + 1;
+  }
+  BatchLayout L;
+  if (st == DM_OK) {
+    layout_batch(P, L);
+    st = ensure_ws(h, L.total);
+  }
+  if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(h->ws), s);
+  for (int i = 0; i < planned; ++i) unpin_band(h, &P[i].g, &P[i].psf);
+  if (st != DM_OK) return st;
+  return end_call(h, s);
 }
 
 dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev, int64_t n,
@@ -820,6 +1073,397 @@ dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g,
   tm.done();
   HIP_TRY(launch_points_finalize(mode, gc, kf, n, part, sp.n_chunks, info, reinterpret_cast<float2*>(out_dev), s));
   return end_call(h, s);
+}
+
+}  // extern "C"
+
+// =============================================================== serving
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ResidentMesh {
+  float* verts = nullptr;
+  int32_t nv = 0;
+  dm_topology* topo = nullptr;
+  int pending = 0;
+};
+
+struct ServeReq {
+  dm_serve_request r{};
+  dm_request req{};       // expanded form handed to the batch engine
+  dm_status status = DM_ERR_BUSY;   // DM_ERR_BUSY while pending
+  int32_t batch = 0;
+  double t_submit = 0.0, t_launch = 0.0, t_done = 0.0;
+};
+
+struct Inflight {
+  std::vector<uint64_t> tickets;
+  hipEvent_t ev = nullptr;
+  size_t bytes = 0;
+  int slot = 0;
+  void* mem = nullptr;    // fallback allocation when the stream-ordered pool is unavailable
+};
+
+}  // namespace
+
+struct dm_server {
+  dm_handle* h = nullptr;
+  dm_server_config cfg{};
+  bool pools = true;
+  std::vector<hipStream_t> streams;
+  std::vector<bool> busy;
+  std::vector<hipEvent_t> event_pool;
+  std::mutex hmu;                          // serialises use of the handle
+  std::mutex mu;                           // queue, requests, in-flight list, stats
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, ServeReq> reqs;
+  std::unordered_map<int32_t, ResidentMesh> meshes;
+  std::vector<Inflight> inflight;
+  size_t inflight_bytes = 0;
+  uint64_t next_ticket = 1;
+  int32_t next_mesh = 1;
+  bool stop = false;
+  dm_server_stats stats{};
+  std::thread worker;
+};
+
+namespace {
+
+void finish_locked(dm_server* S, uint64_t t, dm_status st, int32_t batch) {
+  auto it = S->reqs.find(t);
+  if (it == S->reqs.end()) return;
+  it->second.status = st;
+  it->second.batch = batch;
+  it->second.t_done = now_ms();
+  auto m = S->meshes.find(it->second.r.mesh_id);
+  if (m != S->meshes.end()) m->second.pending--;
+  if (st == DM_OK)
+    S->stats.completed++;
+  else
+    S->stats.rejected++;
+}
+
+// Retires finished batches (mu held).
+void retire_locked(dm_server* S) {
+  bool any = false;
+  for (size_t i = 0; i < S->inflight.size();) {
+    Inflight& b = S->inflight[i];
+    const hipError_t q = hipEventQuery(b.ev);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    const dm_status st = q == hipSuccess ? DM_OK : DM_ERR_DEVICE;
+    for (uint64_t t : b.tickets) finish_locked(S, t, st, (int32_t)b.tickets.size());
+    if (b.mem) (void)hipFree(b.mem);
+    S->event_pool.push_back(b.ev);
+    S->busy[b.slot] = false;
+    S->inflight_bytes -= std::min(S->inflight_bytes, b.bytes);
+    S->inflight.erase(S->inflight.begin() + (long)i);
+    any = true;
+  }
+  if (any) S->cv_done.notify_all();
+}
+
+// Plans and launches one batch from `take` on stream slot `slot`.  Requests
+// that do not fit the budget next to the in-flight batches go back to the
+// front of the queue.
+size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
+  hipStream_t s = S->streams[(size_t)slot];
+  std::vector<ReqPlan> P;
+  std::vector<uint64_t> ids;
+  std::vector<uint64_t> back;
+  std::vector<std::pair<uint64_t, dm_status>> failed;
+  size_t used = 0, inflight_bytes;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    inflight_bytes = S->inflight_bytes;
+  }
+  std::lock_guard<std::mutex> hl(S->hmu);
+  dm_handle* h = S->h;
+  const size_t budget = S->cfg.hbm_budget_bytes;
+  P.reserve(take.size());
+  for (size_t i = 0; i < take.size(); ++i) {
+    const dm_request* rq;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      rq = &S->reqs[take[i]].req;
+    }
+    ReqPlan pl;
+    fill_plan(pl, *rq);
+    dm_status st = plan_request(h, pl, s, true);
+    if (st != DM_OK) {
+      failed.push_back({take[i], st});
+      continue;
+    }
+    const size_t need = align_up(pl.bytes) + 4096;
+    if (budget && need > budget) {
+      unpin_band(h, &pl.g, &pl.psf);
+      failed.push_back({take[i], DM_ERR_BUDGET});
+      continue;
+    }
+    if (budget && inflight_bytes + used + need > budget && !P.empty()) {
+      unpin_band(h, &pl.g, &pl.psf);
+      back.assign(take.begin() + (long)i, take.end());
+      break;
+    }
+    if (budget && inflight_bytes + used + need > budget) {   // wait for memory to free up
+      unpin_band(h, &pl.g, &pl.psf);
+      back.assign(take.begin() + (long)i, take.end());
+      break;
+    }
+    used += need;
+    P.push_back(pl);
+    ids.push_back(take[i]);
+  }
+  Inflight b;
+  dm_status st = DM_OK;
+  if (!P.empty()) {
+    BatchLayout L;
+    layout_batch(P, L);
+    b.bytes = L.total;
+    void* mem = nullptr;
+    hipError_t e = S->pools ? hipMallocAsync(&mem, L.total, s) : hipMalloc(&mem, L.total);
+    if (e != hipSuccess) st = fail(DM_ERR_DEVICE, "workspace allocation: %s", hipGetErrorString(e));
+    if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(mem), s);
+    if (S->pools && mem) (void)hipFreeAsync(mem, s);
+    if (!S->pools) b.mem = mem;
+    if (S->event_pool.empty()) {
+      hipEvent_t ev;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) S->event_pool.push_back(ev);
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!S->event_pool.empty()) {
+      b.ev = S->event_pool.back();
+      S->event_pool.pop_back();
+    }
+    if (st == DM_OK && b.ev) st = hipEventRecord(b.ev, s) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
+    for (auto& pl : P) unpin_band(h, &pl.g, &pl.psf);
+    const double t = now_ms();
+    if (st == DM_OK && b.ev) {
+      b.tickets = ids;
+      b.slot = slot;
+      for (uint64_t id : ids) S->reqs[id].t_launch = t;
+      S->inflight.push_back(b);
+      S->busy[(size_t)slot] = true;
+      S->inflight_bytes += b.bytes;
+      S->stats.peak_inflight_bytes = std::max(S->stats.peak_inflight_bytes, S->inflight_bytes);
+      S->stats.batches++;
+    } else {
+      if (b.ev) S->event_pool.push_back(b.ev);
+      if (b.mem) (void)hipFree(b.mem);
+      for (uint64_t id : ids) finish_locked(S, id, st == DM_OK ? DM_ERR_DEVICE : st, (int32_t)ids.size());
+    }
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto& f : failed) finish_locked(S, f.first, f.second, 0);
+  for (auto it = back.rbegin(); it != back.rend(); ++it) S->queue.push_front(*it);
+  if (!failed.empty() || st != DM_OK) S->cv_done.notify_all();
+  return P.size() + failed.size();
+}
+
+void serve_loop(dm_server* S) {
+  (void)hipSetDevice(S->h->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    retire_locked(S);
+    if (S->stop && S->queue.empty() && S->inflight.empty()) break;
+    int slot = -1;
+    for (size_t i = 0; i < S->busy.size(); ++i)
+      if (!S->busy[i]) {
+        slot = (int)i;
+        break;
+      }
+    const bool mem_free = !S->cfg.hbm_budget_bytes || S->inflight.empty() ||
+                          S->inflight_bytes < S->cfg.hbm_budget_bytes;
+    if (slot >= 0 && !S->queue.empty() && mem_free) {
+      std::vector<uint64_t> take;
+      while ((int)take.size() < S->cfg.max_batch && !S->queue.empty()) {
+        take.push_back(S->queue.front());
+        S->queue.pop_front();
+      }
+      lk.unlock();
+      const size_t handled = launch_batch(S, slot, std::move(take));
+      lk.lock();
+      // nothing fitted next to the in-flight work: wait for a batch to finish
+      if (handled == 0) S->cv_work.wait_for(lk, std::chrono::microseconds(20));
+      continue;
+    }
+    if (S->inflight.empty())
+      S->cv_work.wait(lk);
+    else
+      S->cv_work.wait_for(lk, std::chrono::microseconds(20));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+dm_status dm_server_create(int device, const dm_server_config* cfg, dm_server** out) {
+  g_err.clear();
+  if (!cfg || !out) return fail(DM_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (cfg->max_batch < 1 || cfg->max_inflight < 1 || cfg->max_inflight > 8 || cfg->queue_capacity < 1)
+    return fail(DM_ERR_ARG, "bad server configuration");
+  dm_handle* h = nullptr;
+  DM_TRY(dm_create(&h, device, 0));
+  auto S = std::make_unique<dm_server>();
+  S->h = h;
+  S->cfg = *cfg;
+  DeviceGuard dg(device);
+  int pools = 0;
+  if (hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device) != hipSuccess) pools = 0;
+  S->pools = pools != 0;
+  for (int i = 0; i < cfg->max_inflight; ++i) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
+      dm_destroy(h);
+      return fail(DM_ERR_DEVICE, "stream creation failed");
+    }
+    S->streams.push_back(st);
+    S->busy.push_back(false);
+  }
+  dm_server* raw = S.release();
+  raw->worker = std::thread(serve_loop, raw);
+  *out = raw;
+  return DM_OK;
+}
+
+dm_status dm_server_destroy(dm_server* S) {
+  g_err.clear();
+  if (!S) return DM_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  {
+    DeviceGuard dg(S->h->device);
+    (void)hipDeviceSynchronize();
+    for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
+    for (auto& kv : S->meshes) {
+      dm_topology_destroy(kv.second.topo);
+      (void)hipFree(kv.second.verts);
+    }
+  }
+  dm_destroy(S->h);
+  delete S;
+  return DM_OK;
+}
+
+dm_status dm_server_mesh_add(dm_server* S, const float* verts_host, int32_t n_verts, const int32_t* faces_host,
+                             int32_t n_faces, int32_t* mesh_id) {
+  g_err.clear();
+  if (!S || !mesh_id || (n_verts > 0 && !verts_host)) return fail(DM_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> hl(S->hmu);
+  DeviceGuard dg(S->h->device);
+  ResidentMesh m;
+  m.nv = n_verts;
+  DM_TRY(dm_topology_create(S->h, faces_host, n_faces, n_verts, 0, &m.topo));
+  hipError_t e = hipMalloc(&m.verts, std::max<size_t>(4, (size_t)n_verts * 3 * sizeof(float)));
+  if (e == hipSuccess && n_verts > 0)
+    e = hipMemcpy(m.verts, verts_host, (size_t)n_verts * 3 * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dm_topology_destroy(m.topo);
+    if (m.verts) (void)hipFree(m.verts);
+    return fail(DM_ERR_DEVICE, "mesh upload: %s", hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  *mesh_id = S->next_mesh++;
+  S->meshes[*mesh_id] = m;
+  return DM_OK;
+}
+
+dm_status dm_server_mesh_remove(dm_server* S, int32_t mesh_id) {
+  g_err.clear();
+  if (!S) return fail(DM_ERR_ARG, "NULL server");
+  ResidentMesh m;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->meshes.find(mesh_id);
+    if (it == S->meshes.end()) return fail(DM_ERR_STATE, "unknown mesh %d", mesh_id);
+    if (it->second.pending > 0) return fail(DM_ERR_STATE, "mesh %d has pending requests", mesh_id);
+    m = it->second;
+    S->meshes.erase(it);
+  }
+  std::lock_guard<std::mutex> hl(S->hmu);
+  DeviceGuard dg(S->h->device);
+  dm_topology_destroy(m.topo);
+  (void)hipFree(m.verts);
+  return DM_OK;
+}
+
+dm_status dm_submit(dm_server* S, const dm_serve_request* r, uint64_t* ticket) {
+  g_err.clear();
+  if (!S || !r || !ticket) return fail(DM_ERR_ARG, "NULL argument");
+  DM_TRY(check_grid(&r->grid));
+  DM_TRY(check_psf(&r->psf));
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (S->stop) return fail(DM_ERR_STATE, "server is shutting down");
+  auto it = S->meshes.find(r->mesh_id);
+  if (it == S->meshes.end()) return fail(DM_ERR_ARG, "unknown mesh %d", r->mesh_id);
+  ServeReq q;
+  q.r = *r;
+  q.req.mesh.verts_dev = it->second.verts;
+  q.req.mesh.n_verts = it->second.nv;
+  q.req.mesh.topo = it->second.topo;
+  q.req.psf = r->psf;
+  q.req.grid = r->grid;
+  q.req.dL_dimage_dev = r->dL_dimage_dev;
+  q.req.image_dev = r->image_dev;
+  q.req.dL_dverts_dev = r->dL_dverts_dev;
+  q.req.dL_dsigma_dev = r->dL_dsigma_dev;
+  DM_TRY(check_request(q.req, 0));
+  if ((int)S->queue.size() >= S->cfg.queue_capacity) return fail(DM_ERR_BUSY, "queue full");
+  q.t_submit = now_ms();
+  const uint64_t t = S->next_ticket++;
+  S->reqs[t] = q;
+  it->second.pending++;
+  S->queue.push_back(t);
+  S->stats.submitted++;
+  *ticket = t;
+  lk.unlock();
+  S->cv_work.notify_one();
+  return DM_OK;
+}
+
+dm_status dm_poll(dm_server* S, uint64_t ticket, int blocking, dm_serve_result* out) {
+  g_err.clear();
+  if (!S) return fail(DM_ERR_ARG, "NULL server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(DM_ERR_STATE, "unknown ticket");
+  while (it->second.status == DM_ERR_BUSY) {
+    if (!blocking) return DM_ERR_BUSY;
+    S->cv_done.wait(lk);
+    it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(DM_ERR_STATE, "ticket vanished");
+  }
+  if (out) {
+    out->status = it->second.status;
+    out->batch_size = it->second.batch;
+    out->queue_ms = it->second.t_launch > 0 ? it->second.t_launch - it->second.t_submit : 0.0;
+    out->total_ms = it->second.t_done - it->second.t_submit;
+  }
+  S->reqs.erase(it);
+  return DM_OK;
+}
+
+dm_status dm_server_stats_read(dm_server* S, dm_server_stats* out) {
+  if (!S || !out) return fail(DM_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->stats;
+  out->mean_batch = S->stats.batches ? (double)(S->stats.completed) / (double)S->stats.batches : 0.0;
+  return DM_OK;
 }
 
 }  // extern "C"

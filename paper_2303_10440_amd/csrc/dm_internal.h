@@ -46,7 +46,28 @@ constexpr float PHASE_GRID = 4096.0f;   // 2^12
 // Band-entry record for the VJP sweep: 8 floats (one 32-byte scalar load).
 //  {kx, ky, kz, Wr}, {Wi, xi_x, xi_y, xi_z}
 
+// Work item of the persistent batched sweep: one 256-wide tile of one
+// request's forward sweep (kind 0: lanes = band entries x0.., triangle chunk c)
+// or gradient sweep (kind 1: lanes = triangles x0.., entry chunk c).
+struct SweepItem {
+  int kind, req, x0, c;
+};
+
+// Per-request pointers and chunking for the batched sweep.
+struct SweepReq {
+  int mode, nE, nt, tpc, epc, pad;
+  const float4* kf;
+  const float* rec;
+  float2* fpart;       // [fwd chunks][nE]
+  const float4* erec;  // [nE][2]
+  float* vpart;        // [vjp chunks][NC][nt]
+};
+
+constexpr int SWEEP_THREADS = 256;
+
 // ---- launchers (defined in dm_kernels.hip); all enqueue on `s` ----
+hipError_t launch_batch_sweep(const SweepItem* items, int n_items, const SweepReq* reqs, int* counter, int blocks,
+                              hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_band_count(const GridC& g, const double* sigma6, double qmax, int32_t* cnt, int64_t n_slots,
                              hipStream_t s);
@@ -66,14 +87,18 @@ hipError_t launch_fwd_finalize(int mode, const GridC& g, BandDev b, const float2
                                const MeshInfo* info, float2* spec_out, float2* xhalf, hipStream_t s);
 hipError_t launch_spec_scatter(const GridC& g, BandDev b, const float2* spec, float2* xhalf, hipStream_t s);
 
-hipError_t launch_adjoint(int mode, const GridC& g, BandDev b, const float2* ghat, const MeshInfo* info,
-                          const float2* spec, float4* erec, double* dsig_part, int dsig_blocks, hipStream_t s);
+hipError_t launch_adjoint(int mode, const GridC& g, BandDev b, const float2* ghat, const MeshInfo* info, float4* erec,
+                          hipStream_t s);
+hipError_t launch_dsig(const GridC& g, BandDev b, const float2* ghat, const float2* spec, double* dsig_part,
+                       int dsig_blocks, hipStream_t s);
 int adjoint_blocks(const GridC& g);
 hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hipStream_t s);
 
 hipError_t launch_vjp_sweep(int mode, const float* tri_rec, int nt, const float4* erec, int64_t nE,
                             int ents_per_chunk, int n_chunks, float* part, hipStream_t s);
-hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* red, hipStream_t s);
+int vjp_reduce_groups(int n_chunks);
+hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* tmp, float* red,
+                             hipStream_t s);
 hipError_t launch_surface_scalar(const float* red, const float* tri_rec, int nt, const MeshInfo* info,
                                  double* out_R, hipStream_t s);
 hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, int nt,

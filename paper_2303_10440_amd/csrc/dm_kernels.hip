@@ -38,19 +38,24 @@ constexpr double TWO_PI_D = 6.283185307179586476925286766559;
 // Series branch when the node spread is below one radian.
 constexpr float SERIES_REV = 0.15915494309189535f;   // 1 / (2 pi)
 
-__device__ __forceinline__ float reduce_rev(float r) { return r - __builtin_rintf(r); }
-
 // e^{-2 pi i r} for r in revolutions, r already in [-1/2, 1/2].
 __device__ __forceinline__ void cis_neg(float r, float& c, float& s_neg) {
   c = __builtin_amdgcn_cosf(r);
   s_neg = -__builtin_amdgcn_sinf(r);
 }
 
+// Branch-free select: both operands are materialised before the choice, so
+// the compiler emits v_cndmask instead of a divergent branch.
+__device__ __forceinline__ float pick(bool c, float a, float b) {
+  asm volatile("" : "+v"(a), "+v"(b));
+  return c ? a : b;
+}
+
 // sin(x)/x for x >= 0 given sin(x): polynomial below 0.5, quotient above.
 __device__ __forceinline__ float sinc_from(float x, float sinx, float inv_x) {
   const float x2 = x * x;
   const float p = fmaf(x2, fmaf(x2, fmaf(x2, -1.9841269841e-4f, 8.3333333333e-3f), -0.16666666667f), 1.0f);
-  return x < 0.5f ? p : sinx * inv_x;
+  return pick(x < 0.5f, p, sinx * inv_x);
 }
 
 // Integer-frequency phase of vertex 1 plus the two relative phases (revolutions).
@@ -63,51 +68,77 @@ __device__ __forceinline__ void tri_phases(float kx, float ky, float kz, const f
   d3 = fmaf(kz, r[11], fmaf(ky, r[10], kx * r[9]));
 }
 
-// f_T = DD3[exp](-2 pi i (t1 + {0, d2, d3})).
-__device__ __forceinline__ void dd3(float t1, float d2, float d3, float& fr, float& fi) {
+// Wrap revolutions into [0, 1) for the hardware sine/cosine (v_fract_f32).
+__device__ __forceinline__ float wrap(float r) { return __builtin_amdgcn_fractf(r); }
+
+// Series coefficients of DD3 about the node mean (centred phases a_p,
+// E2 = sum a_p a_q, E3 = a_0 a_1 a_2):  Phi = pre + i pim.
+__device__ __forceinline__ void series_phi(float E2, float E3, float& pre, float& pim) {
+  pre = fmaf(E2, fmaf(E2, fmaf(E2, 2.4801587302e-5f, 1.3888888889e-3f), 4.1666666667e-2f), 0.5f) -
+        E3 * E3 * 2.4801587302e-5f;
+  pim = E3 * fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
+}
+
+// Reciprocals of S = 2 pi s and of the half gaps x1, x2 clamped at 1/2 (the
+// quotients are only used where x >= 1/2), from one v_rcp_f32.
+struct Recips {
+  float invS, invX1, invX2;
+};
+__device__ __forceinline__ Recips recips(float S, float x1, float x2) {
+  const float X1 = fmaxf(x1, 0.5f), X2 = fmaxf(x2, 0.5f);
+  const float X12 = X1 * X2;
+  const float rinv = __builtin_amdgcn_rcpf(S * X12);
+  const float rS = rinv * S;
+  return {rinv * X12, rS * X2, rS * X1};
+}
+
+// acc += w f_T, f_T = DD3[exp](-2 pi i (t1 + {0, d2, d3})).
+//   spread < 1 rad: series about the node mean;
+//   otherwise (sorted nodes):  f = (i/S) [sinc(pi g2) e^{-2 pi i m_mh} - sinc(pi g1) e^{-2 pi i m_lm}]
+//   with m_lm, m_mh the phases at the midpoints of the lo-mid and mid-hi edges.
+__device__ __forceinline__ void dd3_acc(float t1, float d2, float d3, float w, float& ar, float& ai) {
   const float lo = fminf(fminf(0.0f, d2), d3);
   const float hi = fmaxf(fmaxf(0.0f, d2), d3);
   const float s = hi - lo;
   if (s < SERIES_REV) {
     const float m = (d2 + d3) * (1.0f / 3.0f);
     const float a0 = -TWO_PI_F * m, a1 = TWO_PI_F * (d2 - m), a2 = TWO_PI_F * (d3 - m);
-    const float E2 = fmaf(a0, a1 + a2, a1 * a2);
-    const float E3 = a0 * a1 * a2;
-    const float pre = fmaf(E2, fmaf(E2, fmaf(E2, 2.4801587302e-5f, 1.3888888889e-3f), 4.1666666667e-2f), 0.5f) -
-                      E3 * E3 * 2.4801587302e-5f;
-    const float pim = E3 * fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
-    float c, sn;
-    cis_neg(reduce_rev(t1 + m), c, sn);
-    fr = c * pre - sn * pim;
-    fi = fmaf(c, pim, sn * pre);
+    float pre, pim;
+    series_phi(fmaf(a0, a1 + a2, a1 * a2), a0 * a1 * a2, pre, pim);
+    const float r = wrap(t1 + m);
+    const float c = __builtin_amdgcn_cosf(r), sn = -__builtin_amdgcn_sinf(r);
+    ar = fmaf(w, c * pre - sn * pim, ar);
+    ai = fmaf(w, fmaf(c, pim, sn * pre), ai);
     return;
   }
   const float mid = __builtin_amdgcn_fmed3f(0.0f, d2, d3);
   const float g1 = mid - lo, g2 = hi - mid;
-  const float x1 = PI_F * g1, x2 = PI_F * g2, S = TWO_PI_F * s;
-  const float X1 = fmaxf(x1, 0.5f), X2 = fmaxf(x2, 0.5f);
-  const float rinv = __builtin_amdgcn_rcpf(S * X1 * X2);
-  const float invS = rinv * X1 * X2, invX1 = rinv * S * X2, invX2 = rinv * S * X1;
-  const float sin1 = __builtin_amdgcn_sinf(reduce_rev(0.5f * g1));
-  const float sin2 = __builtin_amdgcn_sinf(reduce_rev(0.5f * g2));
-  const float sg1 = sinc_from(x1, sin1, invX1), sg2 = sinc_from(x2, sin2, invX2);
-  float ch, shn, cp, spn;
-  cis_neg(reduce_rev(0.5f * s), ch, shn);               // e^{-i pi s}
-  cis_neg(reduce_rev(t1 + 0.5f * (lo + mid)), cp, spn);  // phase at the lo-mid midpoint
-  // B = sg2 e^{-i pi s} - sg1 ;  f = G' B (i / S)
-  const float br = fmaf(sg2, ch, -sg1), bi = sg2 * shn;
-  const float gr = cp * br - spn * bi, gi = fmaf(cp, bi, spn * br);
-  fr = -gi * invS;
-  fi = gr * invS;
+  const float x1 = PI_F * g1, x2 = PI_F * g2;
+  const Recips q = recips(TWO_PI_F * s, x1, x2);
+  const float sg1 = sinc_from(x1, __builtin_amdgcn_sinf(wrap(0.5f * g1)), q.invX1);
+  const float sg2 = sinc_from(x2, __builtin_amdgcn_sinf(wrap(0.5f * g2)), q.invX2);
+  const float rlm = wrap(fmaf(0.5f, lo + mid, t1)), rmh = wrap(fmaf(0.5f, mid + hi, t1));
+  const float clm = __builtin_amdgcn_cosf(rlm), slm = __builtin_amdgcn_sinf(rlm);
+  const float cmh = __builtin_amdgcn_cosf(rmh), smh = __builtin_amdgcn_sinf(rmh);
+  // B = sg2 E_mh - sg1 E_lm with E = (cos, -sin);  f = (i/S) B = (-B_i, B_r)/S
+  const float br = fmaf(sg2, cmh, -sg1 * clm);
+  const float bi = fmaf(sg1, slm, -sg2 * smh);
+  const float c = w * q.invS;
+  ar = fmaf(-c, bi, ar);
+  ai = fmaf(c, br, ai);
 }
 
-// f_T and the three DD4_p (repeated node p) in slot order {node 0, d2, d3}.
-struct DD34 {
-  float fr, fi;
-  float dr[3], di[3];
-};
-
-__device__ __forceinline__ void dd34(float t1, float d2, float d3, DD34& o) {
+// One pair of the gradient sweep: with W the adjoint weight of the frequency,
+//   VOLUME:  z[p]  = Re(W DD4_p)            (p over the slots {node 0, d2, d3})
+//   SURFACE: wf    = Re(W f_T), z[p] = Im(W DD4_p)
+// DD4_p is the divided difference with node p repeated (Eq. 10 up to -i xi).
+// Stable branch (sorted nodes, R = i/S, P_x = e^{-2 pi i t_x} the vertex phases,
+// phi1, phi2 the first two phi-functions at -i Gamma_j):
+//   f      = R (P_mid phi1(G2) - P_lo phi1(G1))
+//   DD4_lo = R (f - P_lo phi2(G1)),  DD4_hi = R (P_hi conj phi2(G2) - f),
+//   DD4_mid = R P_mid (phi2(G2) - conj phi2(G1)).
+template <int MODE>
+__device__ __forceinline__ void vjp_pair(float t1, float d2, float d3, float wr, float wi, float& wf, float z[3]) {
   const float lo = fminf(fminf(0.0f, d2), d3);
   const float hi = fmaxf(fmaxf(0.0f, d2), d3);
   const float s = hi - lo;
@@ -116,94 +147,87 @@ __device__ __forceinline__ void dd34(float t1, float d2, float d3, DD34& o) {
     const float a[3] = {-TWO_PI_F * m, TWO_PI_F * (d2 - m), TWO_PI_F * (d3 - m)};
     const float E2 = fmaf(a[0], a[1] + a[2], a[1] * a[2]);
     const float E3 = a[0] * a[1] * a[2];
-    const float pre = fmaf(E2, fmaf(E2, fmaf(E2, 2.4801587302e-5f, 1.3888888889e-3f), 4.1666666667e-2f), 0.5f) -
-                      E3 * E3 * 2.4801587302e-5f;
-    const float pim = E3 * fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
+    float pre, pim;
+    series_phi(E2, E3, pre, pim);
     // d Phi / d e2 and d Phi / d e3 (e2 = -E2, e3 = i E3 of the centred nodes)
     const float p2r = fmaf(E2, fmaf(E2, -7.4404761905e-5f, -2.7777777778e-3f), -4.1666666667e-2f);
     const float p2i = -E3 * fmaf(E2, 1.6534391534e-5f, 3.9682539683e-4f);
     const float p3r = fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
     const float p3i = E3 * fmaf(E2, 1.6534391534e-6f, 4.9603174603e-5f);
-    float c, sn;
-    cis_neg(reduce_rev(t1 + m), c, sn);
-    o.fr = c * pre - sn * pim;
-    o.fi = fmaf(c, pim, sn * pre);
+    const float r = wrap(t1 + m);
+    const float c = __builtin_amdgcn_cosf(r), sn = -__builtin_amdgcn_sinf(r);
+    // WG = W e^{-2 pi i (t1 + m)}
+    const float gr = wr * c - wi * sn, gi = fmaf(wr, sn, wi * c);
+    if (MODE == 1) wf = gr * pre - gi * pim;
     const float third_re = pre * (1.0f / 3.0f), third_im = pim * (1.0f / 3.0f);
     const float e2_23 = E2 * (2.0f / 3.0f);
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
       const float b = fmaf(a[p], a[p], e2_23);
-      const float ar = third_re - a[p] * p2i - b * p3r;
-      const float ai = fmaf(a[p], p2r, third_im) - b * p3i;
-      o.dr[p] = c * ar - sn * ai;
-      o.di[p] = fmaf(c, ai, sn * ar);
+      const float Ar = third_re - a[p] * p2i - b * p3r;
+      const float Ai = fmaf(a[p], p2r, third_im) - b * p3i;
+      z[p] = MODE == 0 ? gr * Ar - gi * Ai : fmaf(gr, Ai, gi * Ar);
     }
     return;
   }
   const float mid = __builtin_amdgcn_fmed3f(0.0f, d2, d3);
   const float g1 = mid - lo, g2 = hi - mid;
-  const float x1 = PI_F * g1, x2 = PI_F * g2, S = TWO_PI_F * s;
-  const float X1 = fmaxf(x1, 0.5f), X2 = fmaxf(x2, 0.5f);
-  const float rinv = __builtin_amdgcn_rcpf(S * X1 * X2);
-  const float invS = rinv * X1 * X2, invX1 = rinv * S * X2, invX2 = rinv * S * X1;
-  float c1, s1n, c2, s2n, cl, sln;
-  cis_neg(reduce_rev(0.5f * g1), c1, s1n);      // h1 = e^{-i pi g1}
-  cis_neg(reduce_rev(0.5f * g2), c2, s2n);      // h2 = e^{-i pi g2}
-  cis_neg(reduce_rev(t1 + lo), cl, sln);        // G_lo
-  const float sg1 = sinc_from(x1, -s1n, invX1), sg2 = sinc_from(x2, -s2n, invX2);
-  // h12 = h1 h2 = e^{-i pi s}
-  const float h12r = c1 * c2 - s1n * s2n, h12i = fmaf(c1, s2n, s1n * c2);
-  // f = G_lo h1 (sg2 h12 - sg1) (i/S)
-  const float br = fmaf(sg2, h12r, -sg1), bi = sg2 * h12i;
-  const float hbr = c1 * br - s1n * bi, hbi = fmaf(c1, bi, s1n * br);
-  const float gbr = cl * hbr - sln * hbi, gbi = fmaf(cl, hbi, sln * hbr);
-  const float fr = -gbi * invS, fi = gbr * invS;
-  // phi2(-i G) = sinc(G/2)^2 / 2 - i psi(G),  psi(G) = (G - sin G) / G^2
+  const float x1 = PI_F * g1, x2 = PI_F * g2;
+  const Recips q = recips(TWO_PI_F * s, x1, x2);
+  const float b1 = wrap(0.5f * g1), b2 = wrap(0.5f * g2), bl = wrap(t1 + lo);
+  const float c1 = __builtin_amdgcn_cosf(b1), s1 = __builtin_amdgcn_sinf(b1);   // h1 = (c1, -s1)
+  const float c2 = __builtin_amdgcn_cosf(b2), s2 = __builtin_amdgcn_sinf(b2);   // h2 = (c2, -s2)
+  const float plr = __builtin_amdgcn_cosf(bl), pli = -__builtin_amdgcn_sinf(bl);  // P_lo
+  const float sg1 = sinc_from(x1, s1, q.invX1), sg2 = sinc_from(x2, s2, q.invX2);
+  // psi(G) = (G - sin G) / G^2: series below G = 1, quotient above (sin G = 2 s c)
   float psi1, psi2;
   {
     const float G = 2.0f * x1, G2 = G * G;
-    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, fmaf(G2, 2.5052108385e-8f, -2.7557319224e-6f),
-                                                    1.9841269841e-4f), -8.3333333333e-3f), 0.16666666667f);
-    const float ig = 0.5f * invX1;
-    const float big = (G - 2.0f * (-s1n) * c1) * ig * ig;
-    psi1 = x1 < 0.5f ? ser : big;
+    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, -2.7557319224e-6f, 1.9841269841e-4f), -8.3333333333e-3f),
+                               0.16666666667f);
+    const float ig = 0.5f * q.invX1;
+    psi1 = pick(x1 < 0.5f, ser, fmaf(-2.0f * s1, c1, G) * ig * ig);
   }
   {
     const float G = 2.0f * x2, G2 = G * G;
-    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, fmaf(G2, 2.5052108385e-8f, -2.7557319224e-6f),
-                                                    1.9841269841e-4f), -8.3333333333e-3f), 0.16666666667f);
-    const float ig = 0.5f * invX2;
-    const float big = (G - 2.0f * (-s2n) * c2) * ig * ig;
-    psi2 = x2 < 0.5f ? ser : big;
+    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, -2.7557319224e-6f, 1.9841269841e-4f), -8.3333333333e-3f),
+                               0.16666666667f);
+    const float ig = 0.5f * q.invX2;
+    psi2 = pick(x2 < 0.5f, ser, fmaf(-2.0f * s2, c2, G) * ig * ig);
   }
-  const float p1r = 0.5f * sg1 * sg1, p1i = -psi1;
-  const float p2r = 0.5f * sg2 * sg2, p2i = -psi2;
-  // D_lo = (i/S) (f - G_lo phi2_1)
-  const float gl1r = cl * p1r - sln * p1i, gl1i = fmaf(cl, p1i, sln * p1r);
-  const float ulr = fr - gl1r, uli = fi - gl1i;
-  // D_hi = (i/S) (G_lo e^{-iS} conj(phi2_2) - f),  e^{-iS} = h12^2
-  const float eSr = h12r * h12r - h12i * h12i, eSi = 2.0f * h12r * h12i;
-  const float gSr = cl * eSr - sln * eSi, gSi = fmaf(cl, eSi, sln * eSr);
-  const float uhr = fmaf(gSr, p2r, gSi * p2i) - fr;        // (gS)(p2r - i p2i)
-  const float uhi = gSi * p2r - gSr * p2i - fi;
-  // D_mid = (i/S) G_lo e^{-i G1} (phi2_2 - conj(phi2_1)),  e^{-iG1} = h1^2
-  const float e1r = c1 * c1 - s1n * s1n, e1i = 2.0f * c1 * s1n;
-  const float g1r = cl * e1r - sln * e1i, g1i = fmaf(cl, e1i, sln * e1r);
-  const float qr = p2r - p1r, qi = p2i + p1i;
-  const float umr = g1r * qr - g1i * qi, umi = fmaf(g1r, qi, g1i * qr);
-  // multiply by i/S: (x + iy) i / S = (-y + i x) / S
-  const float Dlor = -uli * invS, Dloi = ulr * invS;
-  const float Dhir = -uhi * invS, Dhii = uhr * invS;
-  const float Dmir = -umi * invS, Dmii = umr * invS;
-  o.fr = fr;
-  o.fi = fi;
+  // P_mid = P_lo h1^2, P_hi = P_mid h2^2
+  const float e1r = fmaf(c1, c1, -s1 * s1), e1i = -2.0f * c1 * s1;
+  const float e2r = fmaf(c2, c2, -s2 * s2), e2i = -2.0f * c2 * s2;
+  const float pmr = plr * e1r - pli * e1i, pmi = fmaf(plr, e1i, pli * e1r);
+  const float phr = pmr * e2r - pmi * e2i, phi = fmaf(pmr, e2i, pmi * e2r);
+  // phi1 = h sinc ; phi2 = sinc^2/2 - i psi
+  const float q1r = c1 * sg1, q1i = -s1 * sg1, q2r = c2 * sg2, q2i = -s2 * sg2;
+  const float f1r = 0.5f * sg1 * sg1, f1i = -psi1, f2r = 0.5f * sg2 * sg2, f2i = -psi2;
+  // F0 = P_mid phi1_2 - P_lo phi1_1 ; f = (i/S) F0
+  const float F0r = (pmr * q2r - pmi * q2i) - (plr * q1r - pli * q1i);
+  const float F0i = fmaf(pmr, q2i, pmi * q2r) - fmaf(plr, q1i, pli * q1r);
+  const float fr = -F0i * q.invS, fi = F0r * q.invS;
+  // W' = W (i/S)
+  const float Wr = -wi * q.invS, Wi = wr * q.invS;
+  if (MODE == 1) wf = wr * fr - wi * fi;
+  // brackets
+  const float blr = fr - (plr * f1r - pli * f1i), bli = fi - fmaf(plr, f1i, pli * f1r);
+  const float bhr = fmaf(phr, f2r, phi * f2i) - fr, bhi = (phi * f2r - phr * f2i) - fi;
+  const float dr = f2r - f1r, di = f2i + f1i;
+  const float bmr = pmr * dr - pmi * di, bmi = fmaf(pmr, di, pmi * dr);
+  float zl, zh, zm;
+  if (MODE == 0) {
+    zl = Wr * blr - Wi * bli;
+    zh = Wr * bhr - Wi * bhi;
+    zm = Wr * bmr - Wi * bmi;
+  } else {
+    zl = fmaf(Wr, bli, Wi * blr);
+    zh = fmaf(Wr, bhi, Wi * bhr);
+    zm = fmaf(Wr, bmi, Wi * bmr);
+  }
   const float v[3] = {0.0f, d2, d3};
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    const bool is_lo = v[p] == lo, is_hi = v[p] == hi;
-    o.dr[p] = is_lo ? Dlor : (is_hi ? Dhir : Dmir);
-    o.di[p] = is_lo ? Dloi : (is_hi ? Dhii : Dmii);
-  }
+  for (int p = 0; p < 3; ++p) z[p] = v[p] == lo ? zl : (v[p] == hi ? zh : zm);
 }
 
 // ------------------------------------------------------------- the band
@@ -478,13 +502,10 @@ __global__ void __launch_bounds__(PREP_T) k_prep_totals(const double* __restrict
 // ------------------------------------------------------------ forward sweep
 constexpr int SWEEP_T = 256;
 
+// Forward sweep over one tile: lane = band entry e, triangles [t0, t1).
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_fwd_sweep(const float4* __restrict__ kf, int nE,
-                                                         const float* __restrict__ rec, int nt, int tpc,
-                                                         float2* __restrict__ part) {
-  const int e = blockIdx.x * SWEEP_T + threadIdx.x;
-  const int t0 = blockIdx.y * tpc;
-  const int t1 = min(nt, t0 + tpc);
+__device__ __forceinline__ void fwd_tile(const float4* __restrict__ kf, int nE, const float* __restrict__ rec, int t0,
+                                         int t1, int e, float2* __restrict__ part_row) {
   float kx = 0.0f, ky = 0.0f, kz = 0.0f;
   if (e < nE) {
     const float4 q = kf[e];
@@ -495,14 +516,21 @@ __global__ void __launch_bounds__(SWEEP_T) k_fwd_sweep(const float4* __restrict_
   float ar = 0.0f, ai = 0.0f;
   for (int t = t0; t < t1; ++t) {
     const float* r = rec + (size_t)t * TRI_REC;
-    float tv, d2, d3, fr, fi;
+    float tv, d2, d3;
     tri_phases(kx, ky, kz, r, tv, d2, d3);
-    dd3(tv, d2, d3, fr, fi);
     const float w = MODE == 0 ? fmaf(kz, r[14], fmaf(ky, r[13], kx * r[12])) : r[12];
-    ar = fmaf(w, fr, ar);
-    ai = fmaf(w, fi, ai);
+    dd3_acc(tv, d2, d3, w, ar, ai);
   }
-  if (e < nE) part[(size_t)blockIdx.y * nE + e] = make_float2(ar, ai);
+  if (e < nE) part_row[e] = make_float2(ar, ai);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(SWEEP_T) k_fwd_sweep(const float4* __restrict__ kf, int nE,
+                                                         const float* __restrict__ rec, int nt, int tpc,
+                                                         float2* __restrict__ part) {
+  const int t0 = blockIdx.y * tpc;
+  fwd_tile<MODE>(kf, nE, rec, t0, min(nt, t0 + tpc), blockIdx.x * SWEEP_T + threadIdx.x,
+                 part + (size_t)blockIdx.y * nE);
 }
 
 // Phase factor e^{-i xi.(c - origin)} for integer frequency k (float32 after
@@ -580,13 +608,36 @@ __global__ void k_spec_scatter(GridC g, BandDev b, const float2* __restrict__ sp
 constexpr int ADJ_T = 256;
 
 template <int MODE>
-__global__ void __launch_bounds__(ADJ_T) k_adjoint(GridC g, BandDev b, const float2* __restrict__ ghat,
-                                                     const MeshInfo* __restrict__ info,
-                                                     const float2* __restrict__ spec, float4* __restrict__ erec,
-                                                     double* __restrict__ dsig_part) {
+__global__ void k_adjoint(GridC g, BandDev b, const float2* __restrict__ ghat, const MeshInfo* __restrict__ info,
+                          float4* __restrict__ erec) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.n_pos) return;
+  const int32_t m = b.map[p];
+  if (m < 0) return;
+  const float inv_area = MODE == 1 ? (float)(1.0 / info->area) : 1.0f;
+  const int iz = (int)(p % g.n2h);
+  const float cp = (iz == 0 || ((g.n2 & 1) == 0 && iz == g.n2 / 2)) ? 1.0f : 2.0f;
+  const float2 G = ghat[p];
+  const int e0 = m & 0x3fffffff, cntm1 = (m >> 30) & 1;
+  for (int e = e0; e <= e0 + cntm1; ++e) {
+    const float4 k = b.kf[e];
+    float pr, pi;
+    ref_phase(info, k.x, k.y, k.z, pr, pi);
+    // W = c_p w_alias h_hat conj(G) e^{-i xi.(c-o)} / (Lx Ly Lz) [/ area]
+    const float a = cp * b.wgt[e] * k.w * g.inv_LV * inv_area;
+    const float wr = a * (G.x * pr + G.y * pi);
+    const float wi = a * (G.x * pi - G.y * pr);
+    erec[2 * e] = make_float4(k.x, k.y, k.z, wr);
+    erec[2 * e + 1] = make_float4(wi, k.x * g.two_pi_over_L[0], k.y * g.two_pi_over_L[1], k.z * g.two_pi_over_L[2]);
+  }
+}
+
+// PSF gradient partials: dL/dSigma_ab = sum_k c_p w h_hat Re[conj(G) u] (-1/2 xi_a xi_b)(2 - delta_ab) / LV,
+// block sums in float64, reduced in a fixed order by k_dsig_final.
+__global__ void __launch_bounds__(ADJ_T) k_dsig(GridC g, BandDev b, const float2* __restrict__ ghat,
+                                                  const float2* __restrict__ spec, double* __restrict__ dsig_part) {
   __shared__ double sh[ADJ_T];
   double d6[6] = {0, 0, 0, 0, 0, 0};
-  const float inv_area = MODE == 1 ? (float)(1.0 / info->area) : 1.0f;
   for (int64_t p = (int64_t)blockIdx.x * ADJ_T + threadIdx.x; p < b.n_pos; p += (int64_t)gridDim.x * ADJ_T) {
     const int32_t m = b.map[p];
     if (m < 0) continue;
@@ -596,40 +647,26 @@ __global__ void __launch_bounds__(ADJ_T) k_adjoint(GridC g, BandDev b, const flo
     const int e0 = m & 0x3fffffff, cntm1 = (m >> 30) & 1;
     for (int e = e0; e <= e0 + cntm1; ++e) {
       const float4 k = b.kf[e];
-      const float base = cp * b.wgt[e] * k.w * g.inv_LV;
-      float pr, pi;
-      ref_phase(info, k.x, k.y, k.z, pr, pi);
-      // W = base conj(G) phase [/ area]
-      const float a = base * inv_area;
-      const float wr = a * (G.x * pr + G.y * pi);
-      const float wi = a * (G.x * pi - G.y * pr);
-      const float xx = k.x * g.two_pi_over_L[0], xy = k.y * g.two_pi_over_L[1], xz = k.z * g.two_pi_over_L[2];
-      erec[2 * e] = make_float4(k.x, k.y, k.z, wr);
-      erec[2 * e + 1] = make_float4(wi, xx, xy, xz);
-      if (dsig_part) {
-        const float2 u = spec[e];
-        const double val = (double)base * (double)(G.x * u.x + G.y * u.y);
-        const double X = xx, Y = xy, Z = xz;
-        d6[0] += val * (-0.5 * X * X);
-        d6[1] += val * (-0.5 * Y * Y);
-        d6[2] += val * (-0.5 * Z * Z);
-        d6[3] += val * (-X * Y);
-        d6[4] += val * (-X * Z);
-        d6[5] += val * (-Y * Z);
-      }
+      const float2 u = spec[e];
+      const double val = (double)(cp * b.wgt[e] * k.w * g.inv_LV) * (double)(G.x * u.x + G.y * u.y);
+      const double X = k.x * g.two_pi_over_L[0], Y = k.y * g.two_pi_over_L[1], Z = k.z * g.two_pi_over_L[2];
+      d6[0] += val * (-0.5 * X * X);
+      d6[1] += val * (-0.5 * Y * Y);
+      d6[2] += val * (-0.5 * Z * Z);
+      d6[3] += val * (-X * Y);
+      d6[4] += val * (-X * Z);
+      d6[5] += val * (-Y * Z);
     }
   }
-  if (dsig_part) {
-    for (int j = 0; j < 6; ++j) {
-      sh[threadIdx.x] = d6[j];
-      __syncthreads();
-      for (int o = ADJ_T / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) dsig_part[6 * blockIdx.x + j] = sh[0];
+  for (int j = 0; j < 6; ++j) {
+    sh[threadIdx.x] = d6[j];
+    __syncthreads();
+    for (int o = ADJ_T / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
       __syncthreads();
     }
+    if (threadIdx.x == 0) dsig_part[6 * blockIdx.x + j] = sh[0];
+    __syncthreads();
   }
 }
 
@@ -648,14 +685,12 @@ __global__ void __launch_bounds__(64) k_dsig_final(const double* __restrict__ pa
 }
 
 // --------------------------------------------------------------- VJP sweep
+// Gradient sweep over one tile: lane = triangle t, band entries [e0, e1).
+// Writes NC channels to part[j * nt + t] (channel-major rows of one chunk).
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_vjp_sweep(const float* __restrict__ rec, int nt,
-                                                         const float4* __restrict__ erec, int nE, int epc,
-                                                         float* __restrict__ part) {
+__device__ __forceinline__ void vjp_tile(const float* __restrict__ rec, int nt, const float4* __restrict__ erec,
+                                         int e0, int e1, int t, float* __restrict__ part) {
   constexpr int NC = MODE == 0 ? 3 : 10;
-  const int t = blockIdx.x * SWEEP_T + threadIdx.x;
-  const int e0 = blockIdx.y * epc;
-  const int e1 = min(nE, e0 + epc);
   float r[12];
 #pragma unroll
   for (int j = 0; j < 12; ++j) r[j] = 0.0f;
@@ -673,35 +708,88 @@ __global__ void __launch_bounds__(SWEEP_T) k_vjp_sweep(const float* __restrict__
     const float4 A = erec[2 * e], B = erec[2 * e + 1];
     float tv, d2, d3;
     tri_phases(A.x, A.y, A.z, r, tv, d2, d3);
-    DD34 o;
-    dd34(tv, d2, d3, o);
-    const float wr = A.w, wi = B.x;
+    float wf = 0.0f, z[3];
+    vjp_pair<MODE>(tv, d2, d3, A.w, B.x, wf, z);
     if (MODE == 0) {
 #pragma unroll
-      for (int p = 0; p < 3; ++p) acc[p] = fmaf(wr, o.dr[p], fmaf(-wi, o.di[p], acc[p]));
+      for (int p = 0; p < 3; ++p) acc[p] += z[p];
     } else {
-      acc[0] = fmaf(wr, o.fr, fmaf(-wi, o.fi, acc[0]));
+      acc[0] += wf;
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
-        const float im = fmaf(wr, o.di[p], wi * o.dr[p]);
-        acc[1 + 3 * p] = fmaf(im, B.y, acc[1 + 3 * p]);
-        acc[2 + 3 * p] = fmaf(im, B.z, acc[2 + 3 * p]);
-        acc[3 + 3 * p] = fmaf(im, B.w, acc[3 + 3 * p]);
+        acc[1 + 3 * p] = fmaf(z[p], B.y, acc[1 + 3 * p]);
+        acc[2 + 3 * p] = fmaf(z[p], B.z, acc[2 + 3 * p]);
+        acc[3 + 3 * p] = fmaf(z[p], B.w, acc[3 + 3 * p]);
       }
     }
   }
   if (t < nt) {
 #pragma unroll
-    for (int j = 0; j < NC; ++j) part[((size_t)blockIdx.y * NC + j) * nt + t] = acc[j];
+    for (int j = 0; j < NC; ++j) part[(size_t)j * nt + t] = acc[j];
   }
 }
 
-__global__ void k_vjp_reduce(const float* __restrict__ part, int n_chunks, int nc, int nt, float* __restrict__ red) {
+template <int MODE>
+__global__ void __launch_bounds__(SWEEP_T) k_vjp_sweep(const float* __restrict__ rec, int nt,
+                                                         const float4* __restrict__ erec, int nE, int epc,
+                                                         float* __restrict__ part) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
+  const int e0 = blockIdx.y * epc;
+  vjp_tile<MODE>(rec, nt, erec, e0, min(nE, e0 + epc), blockIdx.x * SWEEP_T + threadIdx.x,
+                 part + (size_t)blockIdx.y * NC * nt);
+}
+
+// Persistent sweep over a list of work items from many independent meshes
+// (forward and gradient tiles alike).  Each workgroup takes the next item from
+// a global counter; every item writes its own partial slot, so the results do
+// not depend on which workgroup ran which item.
+__global__ void __launch_bounds__(SWEEP_T) k_batch_sweep(const SweepItem* __restrict__ items, int n_items,
+                                                           const SweepReq* __restrict__ reqs,
+                                                           int* __restrict__ counter) {
+  __shared__ int slot;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(slot);
+    __syncthreads();
+    if (it >= n_items) return;
+    const SweepItem w = items[it];
+    const SweepReq q = reqs[w.req];
+    const int lane = w.x0 + (int)threadIdx.x;
+    if (w.kind == 0) {
+      const int t0 = w.c * q.tpc, t1 = min(q.nt, t0 + q.tpc);
+      float2* row = q.fpart + (size_t)w.c * q.nE;
+      if (q.mode == 0)
+        fwd_tile<0>(q.kf, q.nE, q.rec, t0, t1, lane, row);
+      else
+        fwd_tile<1>(q.kf, q.nE, q.rec, t0, t1, lane, row);
+    } else {
+      const int e0 = w.c * q.epc, e1 = min(q.nE, e0 + q.epc);
+      if (q.mode == 0)
+        vjp_tile<0>(q.rec, q.nt, q.erec, e0, e1, lane, q.vpart + (size_t)w.c * 3 * q.nt);
+      else
+        vjp_tile<1>(q.rec, q.nt, q.erec, e0, e1, lane, q.vpart + (size_t)w.c * 10 * q.nt);
+    }
+  }
+}
+
+// Split reduction of the gradient partials in two fixed-order levels:
+// group g sums chunks [g*per, (g+1)*per), then the groups are summed in order.
+__global__ void k_vjp_reduce_groups(const float* __restrict__ part, int n_chunks, int per, int64_t n,
+                                    float* __restrict__ tmp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = (int64_t)nc * nt;
+  if (i >= n) return;
+  const int c0 = blockIdx.y * per, c1 = min(n_chunks, c0 + per);
+  float s = 0.0f;
+  for (int c = c0; c < c1; ++c) s += part[(size_t)c * n + i];
+  tmp[(size_t)blockIdx.y * n + i] = s;
+}
+
+__global__ void k_vjp_reduce_final(const float* __restrict__ tmp, int groups, int64_t n, float* __restrict__ red) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float s = 0.0f;
-  for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * n + i];
+  for (int g = 0; g < groups; ++g) s += tmp[(size_t)g * n + i];
   red[i] = s;
 }
 
@@ -871,17 +959,31 @@ int adjoint_blocks(const GridC& g) {
   return (int)(b < 1 ? 1 : b);
 }
 
-hipError_t launch_adjoint(int mode, const GridC& g, BandDev b, const float2* ghat, const MeshInfo* info,
-                          const float2* spec, float4* erec, double* dsig_part, int dsig_blocks, hipStream_t s) {
+hipError_t launch_adjoint(int mode, const GridC& g, BandDev b, const float2* ghat, const MeshInfo* info, float4* erec,
+                          hipStream_t s) {
+  const dim3 grid(blocks_for(b.n_pos, 256));
   if (mode == 0)
-    hipLaunchKernelGGL(k_adjoint<0>, dim3(dsig_blocks), dim3(ADJ_T), 0, s, g, b, ghat, info, spec, erec, dsig_part);
+    hipLaunchKernelGGL(k_adjoint<0>, grid, dim3(256), 0, s, g, b, ghat, info, erec);
   else
-    hipLaunchKernelGGL(k_adjoint<1>, dim3(dsig_blocks), dim3(ADJ_T), 0, s, g, b, ghat, info, spec, erec, dsig_part);
+    hipLaunchKernelGGL(k_adjoint<1>, grid, dim3(256), 0, s, g, b, ghat, info, erec);
+  return hipGetLastError();
+}
+
+hipError_t launch_dsig(const GridC& g, BandDev b, const float2* ghat, const float2* spec, double* dsig_part,
+                       int dsig_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_dsig, dim3(dsig_blocks), dim3(ADJ_T), 0, s, g, b, ghat, spec, dsig_part);
   return hipGetLastError();
 }
 
 hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hipStream_t s) {
   hipLaunchKernelGGL(k_dsig_final, dim3(1), dim3(64), 0, s, dsig_part, nblk, out6);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(const SweepItem* items, int n_items, const SweepReq* reqs, int* counter, int blocks,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(counter), (int64_t)1);
+  hipLaunchKernelGGL(k_batch_sweep, dim3((unsigned)blocks), dim3(SWEEP_T), 0, s, items, n_items, reqs, counter);
   return hipGetLastError();
 }
 
@@ -895,10 +997,17 @@ hipError_t launch_vjp_sweep(int mode, const float* tri_rec, int nt, const float4
   return hipGetLastError();
 }
 
-hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* red, hipStream_t s) {
-  const int nc = nchannels(mode);
-  hipLaunchKernelGGL(k_vjp_reduce, dim3(blocks_for((int64_t)nc * nt, 256)), dim3(256), 0, s, part, n_chunks, nc, nt,
-                     red);
+int vjp_reduce_groups(int n_chunks) { return n_chunks < 32 ? n_chunks : 32; }
+
+hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* tmp, float* red,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)nchannels(mode) * nt;
+  const int groups = vjp_reduce_groups(n_chunks);
+  const int per = (n_chunks + groups - 1) / groups;
+  const int used = (n_chunks + per - 1) / per;
+  hipLaunchKernelGGL(k_vjp_reduce_groups, dim3(blocks_for(n, 256), (unsigned)used), dim3(256), 0, s, part, n_chunks,
+                     per, n, tmp);
+  hipLaunchKernelGGL(k_vjp_reduce_final, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const float*)tmp, used, n, red);
   return hipGetLastError();
 }
 

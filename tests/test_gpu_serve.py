@@ -1,0 +1,156 @@
+"""Continuous-batching server: every request's result equals the same request
+run alone, batches form while earlier ones run, admission respects the HBM
+budget, oversize requests are refused, state errors are reported."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from helpers import f32_grid, f32_sigma
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+VOLUME, SURFACE = configs.VOLUME, configs.SURFACE
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_10440_amd as m
+    return m
+
+
+def _cells(n, seed=0):
+    rng = np.random.default_rng(seed)
+    grids = ((24, 28, 20), (32, 32, 32), (40, 36, 24))
+    out = []
+    for i in range(n):
+        c = configs.random_cell(rng, 300, 2500, grids, f"cell{i}", SURFACE if i % 3 == 2 else VOLUME)
+        out.append(c)
+    return out
+
+
+def _buffers(c, seed):
+    import torch
+    g = f32_grid(c.grid)
+    G = torch.tensor(np.random.default_rng(seed).standard_normal(g.n).astype(np.float32), device="cuda:0")
+    img = torch.empty(g.n, device="cuda:0")
+    dv = torch.empty((len(c.V), 3), device="cuda:0")
+    ds = torch.empty(6, device="cuda:0")
+    return g, G, img, dv, ds
+
+
+def test_served_results_equal_alone(dm):
+    import torch
+    say("serve equal alone")
+    cells = _cells(7)
+    srv = dm.Server(0, max_batch=8, max_inflight=2)
+    h = dm.Handle(0)
+    try:
+        ids = [srv.mesh_add(c.V, c.F) for c in cells]
+        bufs = [_buffers(c, i) for i, c in enumerate(cells)]
+        tickets = [srv.submit(mid, f32_sigma(c.sigma), b[0], b[1], b[2], b[3], b[4])
+                   for mid, c, b in zip(ids, cells, bufs)]
+        res = [srv.poll(t) for t in tickets]
+        assert all(r["status"] == 0 for r in res)
+        torch.cuda.synchronize()
+        for c, b in zip(cells, bufs):
+            g, G = b[0], b[1]
+            topo = h.topology(c.F, n_verts=len(c.V))
+            V = torch.tensor(c.V, device="cuda:0")
+            img, dv, ds = dm.batch_run(h, [(V, topo, f32_sigma(c.sigma), g, G)])[0]
+            assert bool((img == b[2]).all()) and bool((dv == b[3]).all()) and bool((ds == b[4]).all())
+        st = srv.stats()
+        assert st["completed"] == len(cells) and st["rejected"] == 0
+    finally:
+        srv.close()
+
+
+def test_continuous_batching_under_staggered_arrivals(dm):
+    import torch
+    say("serve staggered")
+    cells = _cells(24, seed=1)
+    srv = dm.Server(0, max_batch=6, max_inflight=2)
+    try:
+        ids = [srv.mesh_add(c.V, c.F) for c in cells]
+        bufs = [_buffers(c, i) for i, c in enumerate(cells)]
+        tickets = []
+
+        def client():
+            rng = np.random.default_rng(7)
+            for mid, c, b in zip(ids, cells, bufs):
+                tickets.append(srv.submit(mid, f32_sigma(c.sigma), b[0], b[1], b[2], b[3], b[4]))
+                time.sleep(float(rng.exponential(0.002)))
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        res = [srv.poll(t) for t in tickets]
+        assert all(r["status"] == 0 for r in res)
+        assert max(r["batch_size"] for r in res) > 1
+        torch.cuda.synchronize()
+        for b in bufs:
+            assert bool(torch.isfinite(b[2]).all()) and bool(torch.isfinite(b[3]).all())
+        st = srv.stats()
+        assert st["completed"] == len(cells) and st["batches"] < len(cells)
+    finally:
+        srv.close()
+
+
+def test_budget_admission_and_oversize_rejection(dm):
+    say("serve budget")
+    small = _cells(6, seed=2)
+    big = configs.random_cell(np.random.default_rng(9), 3000, 3000, ((128, 128, 128),), "big", VOLUME)
+    budget = 24 << 20
+    srv = dm.Server(0, max_batch=8, max_inflight=2, hbm_budget_bytes=budget)
+    try:
+        ids = [srv.mesh_add(c.V, c.F) for c in small]
+        bid = srv.mesh_add(big.V, big.F)
+        bufs = [_buffers(c, i) for i, c in enumerate(small)]
+        bb = _buffers(big, 99)
+        tickets = [srv.submit(mid, f32_sigma(c.sigma), b[0], b[1], b[2], b[3], b[4])
+                   for mid, c, b in zip(ids, small, bufs)]
+        tb = srv.submit(bid, f32_sigma(big.sigma), bb[0], bb[1], bb[2], bb[3], bb[4])
+        res = [srv.poll(t) for t in tickets]
+        rb = srv.poll(tb)
+        assert all(r["status"] == 0 for r in res)
+        assert rb["status"] == -4          # its footprint alone exceeds the budget
+        st = srv.stats()
+        assert st["peak_inflight_bytes"] <= budget
+        assert st["rejected"] == 1
+        with pytest.raises(dm.DeltamicError):
+            srv.poll(tb)                   # ticket consumed
+    finally:
+        srv.close()
+
+
+def test_mesh_remove_with_pending_request_is_refused(dm):
+    say("serve mesh remove")
+    c = _cells(1, seed=3)[0]
+    srv = dm.Server(0, max_batch=1, max_inflight=1)
+    try:
+        mid = srv.mesh_add(c.V, c.F)
+        b = _buffers(c, 0)
+        t = srv.submit(mid, f32_sigma(c.sigma), b[0], b[1], b[2], b[3], b[4])
+        try:
+            srv.mesh_remove(mid)
+            removed = True
+        except dm.DeltamicError as e:
+            assert e.status == -8
+            removed = False
+        assert srv.poll(t)["status"] == 0 or removed
+        if not removed:
+            srv.mesh_remove(mid)
+        with pytest.raises(dm.DeltamicError):
+            srv.submit(mid, f32_sigma(c.sigma), b[0], b[1], b[2], b[3], b[4])
+    finally:
+        srv.close()
