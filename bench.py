@@ -90,6 +90,103 @@ def cpu_baseline(case, grid, sigma, mode, seconds: float):
                       f"{tf_tot + tv_tot:.1f} s (fwd {pairs / tf_tot:.3g} pairs/s, grad {pairs / tv_tot:.3g} pairs/s)"}
 
 
+def bench_batch(dm, h, reps: int = 2) -> dict:
+    """cfg4: 64 independent deformed cells (1k-20k triangles, grids 64^3 /
+    96^3 / 128x128x64, sigma_z ~ U[1.5, 3]): one dm_batch_run for all of them
+    against 64 dm_render_vjp calls in a row on the same stream."""
+    import torch
+    from workloads import configs
+    cases = configs.cfg4()
+    rng = np.random.default_rng(1)
+    reqs, pairs = [], 0.0
+    for c in cases:
+        topo = h.topology(c.F, n_verts=len(c.V))
+        V = torch.tensor(c.V, device="cuda:0")
+        G = torch.tensor(rng.standard_normal(c.grid.n).astype(np.float32), device="cuda:0")
+        reqs.append((V, topo, c.sigma, c.grid, G))
+        pairs += float(dm.band_size(h, c.grid, c.sigma)) * c.F.shape[0]
+    out_b = dm.batch_run(h, reqs)
+    out_l = [dm.render_vjp(h, *r, want_image=True) for r in reqs]
+    torch.cuda.synchronize()
+    worst = max(float(((a[0] - b[2]).norm() / b[2].norm()).item()) for a, b in zip(out_b, out_l))
+    s = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(s)
+    for _ in range(reps):
+        dm.batch_run(h, reqs)
+    e1.record(s)
+    for _ in range(reps):
+        for r in reqs:
+            dm.render_vjp(h, *r, want_image=True)
+    e2.record(s)
+    torch.cuda.synchronize()
+    tb, tl = e0.elapsed_time(e1) / reps, e1.elapsed_time(e2) / reps
+    return {"workload": "64 deformed cells, n_t log-uniform [1k, 20k], grids {64^3, 96^3, 128x128x64}, "
+                        "sigma_xy = 1, sigma_z ~ U[1.5, 3] voxels, forward + gradient",
+            "pairs": pairs, "batched_ms": tb, "looped_ms": tl, "batched_pairs_per_s": pairs / (tb * 1e-3),
+            "looped_pairs_per_s": pairs / (tl * 1e-3), "speedup": tl / tb, "max_image_rel_diff": worst}
+
+
+def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_inflight: int, pool: int = 32,
+                seed: int = 0) -> dict:
+    """cfg5: Poisson arrivals of forward + gradient requests on resident cells
+    (n_t log-uniform [500, 40k], grids {64^3, 128^3, 256x256x128}); latency is
+    submission to completion as seen by the server."""
+    import torch
+    from workloads import configs
+    cases, t_arr, idx, widx = configs.cfg5_pooled(seed, count, rate, pool, warmup)
+    h = dm.Handle(0)
+    rng = np.random.default_rng(2)
+    Gs = [torch.tensor(rng.standard_normal(c.grid.n).astype(np.float32), device="cuda:0") for c in cases]
+    pairs_of = [float(dm.band_size(h, c.grid, c.sigma)) * c.F.shape[0] for c in cases]
+
+    def run(mb, mi):
+        srv = dm.Server(0, max_batch=mb, max_inflight=mi)
+        ids = [srv.mesh_add(c.V, c.F) for c in cases]
+
+        def submit(i):
+            c = cases[i]
+            img = torch.empty(c.grid.n, device="cuda:0")
+            dv = torch.empty((len(c.V), 3), device="cuda:0")
+            ds = torch.empty(6, device="cuda:0")
+            return srv.submit(ids[i], c.sigma, c.grid, Gs[i], img, dv, ds), (img, dv, ds)
+
+        keep = [submit(int(i)) for i in widx]
+        for t, _ in keep:
+            srv.poll(t)
+        torch.cuda.synchronize()
+        subs, keep, t0 = [], [], time.perf_counter()
+        for k in range(count):
+            while time.perf_counter() - t0 < t_arr[k]:
+                pass
+            ts = time.perf_counter() - t0
+            tk, bufs = submit(int(idx[k]))
+            subs.append((tk, ts))
+            keep.append(bufs)
+        res = [(srv.poll(tk), ts) for tk, ts in subs]
+        st = srv.stats()
+        srv.close()
+        lat = np.array([r["total_ms"] for r, _ in res])
+        done = max(ts * 1e3 + r["total_ms"] for r, ts in res)
+        span_s = (done - subs[0][1] * 1e3) * 1e-3
+        pairs = sum(pairs_of[int(i)] for i in idx)
+        late = max(ts - t_arr[k] for k, (_, ts) in enumerate(subs))
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "throughput_rps": count / span_s, "pairs_per_s": pairs / span_s,
+                "mean_batch": float(st["mean_batch"]), "batches": int(st["batches"]),
+                "max_submit_lateness_ms": 1e3 * float(late),
+                "ok": all(r["status"] == 0 for r, _ in res)}
+
+    out = {"workload": f"{count} Poisson requests at {rate:g}/s on a pool of {pool} resident cells "
+                       "(n_t log-uniform [500, 40k], grids {64^3, 128^3, 256x256x128}, own PSF per cell), "
+                       "forward + gradient each",
+           "rate": rate, "offered_pairs_per_s": rate * float(np.mean([pairs_of[int(i)] for i in idx]))}
+    out["batched"] = run(max_batch, max_inflight)
+    out["plain"] = run(1, 1)
+    out["throughput_gain"] = out["batched"]["throughput_rps"] / out["plain"]["throughput_rps"]
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +195,12 @@ def main() -> int:
     ap.add_argument("--mode", choices=["volume", "surface"], default="volume")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="add the 64-cell batched vs looped comparison")
+    ap.add_argument("--serve", type=float, nargs="*", default=None,
+                    help="add the serving comparison at these arrival rates (req/s)")
+    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -190,6 +293,17 @@ def main() -> int:
         "sweeps": sweeps,
         "roofline": roofline,
     }
+    if args.copy_calibration:
+        x = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 256 << 20
+    if args.batch:
+        out["batched"] = bench_batch(dm, h)
+    if args.serve is not None:
+        out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, g, sigma, mode, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]

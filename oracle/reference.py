@@ -26,6 +26,7 @@ float32 GPU library pass the float32-rounded values).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import pathlib
 import subprocess
@@ -198,7 +199,7 @@ def band_threshold(tau: float) -> float:
     tau = float(tau)
     if tau <= 0.0:
         return np.inf
-    return -2.0 * np.log(tau)
+    return -2.0 * math.log(tau)   # the C library's log, as the band rule specifies
 
 
 def full_grid_k(grid) -> np.ndarray:

@@ -488,10 +488,13 @@ struct ReqPlan {
 
 // Batch chunking depends on the request alone, so a request's result is the
 // same whichever other requests share its batch.
+// At least 640 triangles / 1024 entries per tile so small requests still
+// give long sweeps, at most 8 / 64 chunks so the partials of large requests
+// stay bounded (8 B x entries x 8 and 4 B x channels x triangles x 64).
 SweepPlan plan_fwd_batch(int64_t nE, int nt) {
   SweepPlan sp;
   (void)nE;
-  sp.per_chunk = std::max(1, std::min(nt, 640));
+  sp.per_chunk = std::max(1, std::min(nt, std::max(640, (nt + 7) / 8)));
   sp.n_chunks = (nt + sp.per_chunk - 1) / sp.per_chunk;
   return sp;
 }
@@ -499,7 +502,7 @@ SweepPlan plan_fwd_batch(int64_t nE, int nt) {
 SweepPlan plan_vjp_batch(int64_t nE, int nt) {
   SweepPlan sp;
   (void)nt;
-  sp.per_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nE, 1024));
+  sp.per_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nE, std::max<int64_t>(1024, (nE + 63) / 64)));
   sp.n_chunks = (int)((nE + sp.per_chunk - 1) / sp.per_chunk);
   return sp;
 }

@@ -151,6 +151,19 @@ def cfg5_trace(seed: int = 0, count: int = 2000, rate: float = 200.0, mode: int 
     return t, cases
 
 
+def cfg5_pooled(seed: int = 0, count: int = 200, rate: float = 200.0, pool: int = 32, warmup: int = 20):
+    """cfg5 with resident meshes: a pool of ``pool`` cells drawn from the cfg5
+    distribution (each with its own grid and PSF); request i uses cell
+    idx[i] (uniform over the pool), arrivals Poisson at ``rate``.  Returns
+    (pool_cases, arrival_times_s [count], idx [count], warmup_idx [warmup])."""
+    rng = np.random.default_rng(seed)
+    cases = [random_cell(rng, 500, 40000, SERVE_GRIDS, f"cfg5_pool_{i}") for i in range(pool)]
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    idx = rng.integers(pool, size=count)
+    widx = rng.integers(pool, size=warmup)
+    return cases, t, idx, widx
+
+
 def box_case(lo=(10.25, 11.5, 9.75), hi=(19.5, 17.25, 23.0), n=(32, 32, 32), mode: int = VOLUME,
              sigma_xy: float = 1.0, sigma_z: float = 2.0, tau: float = 1e-3) -> Case:
     """Axis-aligned box: every edge is parallel to a grid axis, so on the

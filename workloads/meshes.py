@@ -91,41 +91,39 @@ def geodesic_sphere(freq: int) -> tuple[np.ndarray, np.ndarray]:
     """Unit geodesic sphere of frequency ``freq``: 20 f^2 faces, 10 f^2 + 2 vertices.
 
     Each icosahedron face is cut into freq^2 triangles on a barycentric grid;
-    grid points are keyed by their integer barycentric weights on global
-    icosahedron vertex ids, so points on shared edges are merged exactly.
+    a grid point is identified by its integer barycentric weights on the 12
+    icosahedron vertices, so points on shared edges and corners merge exactly.
     """
     if freq < 1:
         raise ValueError("freq must be >= 1")
     V0, F0 = icosahedron()
-    index: dict[tuple, int] = {}
-    pts: list[np.ndarray] = []
-
-    def vid(weights: dict[int, int]) -> int:
-        key = tuple(sorted((k, w) for k, w in weights.items() if w > 0))
-        if key not in index:
-            index[key] = len(pts)
-            p = sum(w * V0[k] for k, w in key) / freq
-            pts.append(p)
-        return index[key]
-
-    faces = []
-    for A, B, C in F0:
-        grid = {}
-        for i in range(freq + 1):
-            for j in range(freq + 1 - i):
-                w: dict[int, int] = {}
-                for k, ww in ((A, freq - i - j), (B, i), (C, j)):
-                    w[k] = w.get(k, 0) + ww
-                grid[(i, j)] = vid(w)
-        for i in range(freq):
-            for j in range(freq - i):
-                faces.append((grid[(i, j)], grid[(i + 1, j)], grid[(i, j + 1)]))
-                if i + j < freq - 1:
-                    faces.append((grid[(i + 1, j)], grid[(i + 1, j + 1)], grid[(i, j + 1)]))
-    V = np.array(pts)
+    n = freq
+    ii, jj = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    keep = ii + jj <= n
+    gi, gj = ii[keep], jj[keep]                    # grid points of one face
+    local = -np.ones((n + 1, n + 1), dtype=np.int64)
+    local[gi, gj] = np.arange(len(gi))
+    keys = np.zeros((20 * len(gi), 12), dtype=np.int64)
+    for f, (A, B, C) in enumerate(F0):
+        rows = slice(f * len(gi), (f + 1) * len(gi))
+        keys[rows, A] += n - gi - gj
+        keys[rows, B] += gi
+        keys[rows, C] += gj
+    uniq, inv = np.unique(keys, axis=0, return_inverse=True)
+    inv = inv.reshape(20, len(gi))
+    # triangles of one face in local grid indices, same orientation as (A, B, C)
+    up_i, up_j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    m_up = up_i + up_j < n
+    a, b = up_i[m_up], up_j[m_up]
+    tri_up = np.stack([local[a, b], local[a + 1, b], local[a, b + 1]], 1)
+    m_dn = up_i + up_j < n - 1
+    a, b = up_i[m_dn], up_j[m_dn]
+    tri_dn = np.stack([local[a + 1, b], local[a + 1, b + 1], local[a, b + 1]], 1)
+    tri = np.concatenate([tri_up, tri_dn])
+    F = np.concatenate([inv[f][tri] for f in range(20)]).astype(np.int64)
+    V = (uniq @ V0) / n
     V /= np.linalg.norm(V, axis=1, keepdims=True)
-    F = np.array(faces, dtype=np.int64)
-    assert V.shape[0] == 10 * freq * freq + 2 and F.shape[0] == 20 * freq * freq
+    assert V.shape[0] == 10 * n * n + 2 and F.shape[0] == 20 * n * n
     return V, F
 
 
