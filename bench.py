@@ -45,6 +45,27 @@ ALG = {
 }
 
 
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over this benchmark, each
+# divided by what the same counter reads for a plain device-to-device copy of
+# known size.  Valid only for the kernel source it was measured on: if the
+# hash of the kernel file differs, the benchmark reports traffic as null.
+TRAFFIC = None
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2303_10440_amd", "csrc", "dm_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str):
+    if TRAFFIC is None or TRAFFIC["kernel"] != kernel or TRAFFIC["source_sha256"] != kernel_source_sha256():
+        return None
+    return TRAFFIC["bytes_per_launch"]
+
+
 def flop_eq(kind: str) -> float:
     a = ALG[kind]
     return a["flops"] + TRANS_FLOP_EQ * a["trans"]
@@ -265,9 +286,10 @@ def main() -> int:
     dms = (fwd_ms if dom == "fwd" else vjp_ms) / max(launches, 1)
     per_launch_pairs = (fwd_pairs if dom == "fwd" else vjp_pairs) / max(launches, 1)
     achieved = per_launch_pairs * flop_eq(dkind) / (dms * 1e-3) / 1e12
+    kname = ("k_fwd_sweep" if dom == "fwd" else "k_vjp_lanes") + ("<0>" if mode == configs.VOLUME else "<1>")
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_fwd_sweep" if dom == "fwd" else "k_vjp_sweep",
+                "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(kname),
+                "kernel": kname,
                 "avg_launch_ms": dms, "pairs_per_launch": per_launch_pairs,
                 "flop_eq_per_pair": flop_eq(dkind)}
 

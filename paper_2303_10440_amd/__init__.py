@@ -91,6 +91,10 @@ def _load():
     if not LIB_PATH.exists():
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2303_10440_amd/csrc/build.sh "
                           "(or __graft_entry__.build())")
+    # torch ships its own HIP runtime.  Loading torch first makes the library bind
+    # to that same runtime (matched by soname); loading the library first would
+    # bring in a second HIP/HSA runtime under which torch finds no GPU.
+    import torch  # noqa: F401
     L = ctypes.CDLL(str(LIB_PATH))
     vp, i32, i64, fp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)
     sig = {

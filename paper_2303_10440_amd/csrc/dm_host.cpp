@@ -380,6 +380,7 @@ dm_status check_mesh(const dm_mesh* m, int mode) {
 // Launch geometry of the two sweeps.
 struct SweepPlan {
   int n_chunks = 1, per_chunk = 1;
+  int sub = 1, tpb = 1;   // lane-per-entry gradient sweep: entry chunks per block, triangles per block
 };
 
 SweepPlan plan_fwd(int64_t nE, int nt) {
@@ -395,16 +396,20 @@ SweepPlan plan_fwd(int64_t nE, int nt) {
   return sp;
 }
 
+// Gradient sweep (lane per band entry): n_chunks blocks along the band of
+// sub x VJP_CHUNK entries each, at most 64 of them so the partials stay
+// bounded (4 B x channels x triangles x 64), times triangle chunks of tpb so
+// the grid has about 4096 blocks.
 SweepPlan plan_vjp(int64_t nE, int nt) {
   SweepPlan sp;
-  const int64_t tiles = (nt + 255) / 256;
-  int64_t want = (16384 + tiles - 1) / std::max<int64_t>(tiles, 1);
-  const int64_t maxc = std::max<int64_t>(1, nE / 64);
-  sp.n_chunks = (int)std::max<int64_t>(1, std::min(want, maxc));
-  sp.per_chunk = (int)((nE + sp.n_chunks - 1) / sp.n_chunks);
-  if (sp.per_chunk < 1) sp.per_chunk = 1;
-  sp.n_chunks = (int)((nE + sp.per_chunk - 1) / sp.per_chunk);
-  if (sp.n_chunks < 1) sp.n_chunks = 1;
+  const int64_t units = std::max<int64_t>(1, (nE + VJP_CHUNK - 1) / VJP_CHUNK);
+  sp.sub = (int)((units + 63) / 64);
+  sp.n_chunks = (int)((units + sp.sub - 1) / sp.sub);
+  sp.per_chunk = sp.sub * VJP_CHUNK;
+  const int64_t want = (4096 + sp.n_chunks - 1) / sp.n_chunks;
+  const int64_t most = std::max<int64_t>(1, (nt + 31) / 32);
+  const int64_t tchunks = std::max<int64_t>((nt + VJP_TPB_MAX - 1) / VJP_TPB_MAX, std::min(want, most));
+  sp.tpb = (int)std::max<int64_t>(1, (nt + tchunks - 1) / tchunks);
   return sp;
 }
 
@@ -488,9 +493,10 @@ struct ReqPlan {
 
 // Batch chunking depends on the request alone, so a request's result is the
 // same whichever other requests share its batch.
-// At least 640 triangles / 1024 entries per tile so small requests still
-// give long sweeps, at most 8 / 64 chunks so the partials of large requests
-// stay bounded (8 B x entries x 8 and 4 B x channels x triangles x 64).
+// At least 640 triangles per forward tile so small requests still give long
+// sweeps, at most 8 forward chunks so the partials of large requests stay
+// bounded (8 B x entries x 8).  Gradient items cover sub x VJP_CHUNK entries
+// (at most 64 chunks, as in plan_vjp) and up to VJP_TPB_MAX triangles.
 SweepPlan plan_fwd_batch(int64_t nE, int nt) {
   SweepPlan sp;
   (void)nE;
@@ -500,10 +506,8 @@ SweepPlan plan_fwd_batch(int64_t nE, int nt) {
 }
 
 SweepPlan plan_vjp_batch(int64_t nE, int nt) {
-  SweepPlan sp;
-  (void)nt;
-  sp.per_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nE, std::max<int64_t>(1024, (nE + 63) / 64)));
-  sp.n_chunks = (int)((nE + sp.per_chunk - 1) / sp.per_chunk);
+  SweepPlan sp = plan_vjp(nE, nt);
+  sp.tpb = std::max(1, std::min(nt, VJP_TPB_MAX));
   return sp;
 }
 
@@ -537,7 +541,7 @@ dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch) {
     P.o_fftw = cv.take<char>(P.fp ? std::max(P.fp->work_c2r, P.fp->work_r2c) : 0);
     P.o_gin = P.want_vjp ? cv.take<float>(P.nvox) : 0;
     P.o_ghat = P.want_vjp ? cv.take<float2>(P.b.n_pos) : 0;
-    P.o_erec = vjp_v ? cv.take<float4>(2 * (size_t)P.nE) : 0;
+    P.o_erec = vjp_v ? cv.take<float4>((size_t)ERC * P.nE) : 0;
     P.o_dsp = (P.want_vjp && P.dS) ? cv.take<double>(6 * (size_t)P.adj_blocks) : 0;
     P.o_vpart = vjp_v ? cv.take<float>((size_t)P.vsp.n_chunks * P.nc * P.nt) : 0;
     P.o_red = vjp_v ? cv.take<float>((size_t)P.nc * P.nt) : 0;
@@ -586,8 +590,8 @@ dm_status stage_sweeps(dm_handle* h, ReqPlan& P, hipStream_t s) {
   }
   if (P.want_vjp && P.dV) {
     SweepTimer tm(h, s, 1, (double)P.nE * P.nt);
-    HIP_TRY(launch_vjp_sweep(P.mode, P.ptr<float>(P.o_rec), P.nt, P.ptr<float4>(P.o_erec), P.nE, P.vsp.per_chunk,
-                             P.vsp.n_chunks, P.ptr<float>(P.o_vpart), s));
+    HIP_TRY(launch_vjp_lanes(P.mode, P.gc, P.ptr<float>(P.o_rec), P.nt, P.vsp.tpb, P.vsp.sub, P.vsp.n_chunks,
+                             P.ptr<float4>(P.o_erec), P.nE, P.ptr<float>(P.o_vpart), s));
     tm.done();
   }
   return DM_OK;
@@ -607,9 +611,9 @@ void add_items(const ReqPlan& P, int req, std::vector<SweepItem>& items, std::ve
   if (P.want_vjp && P.dV)
     for (int c = 0; c < P.vsp.n_chunks; ++c) {
       const int64_t ents = std::min<int64_t>(P.nE, (int64_t)(c + 1) * P.vsp.per_chunk) - (int64_t)c * P.vsp.per_chunk;
-      for (int x0 = 0; x0 < P.nt; x0 += SWEEP_THREADS) {
+      for (int x0 = 0; x0 < P.nt; x0 += P.vsp.tpb) {
         items.push_back({1, req, x0, c});
-        cost.push_back(1.9 * (double)ents * (double)std::min(SWEEP_THREADS, P.nt - x0));
+        cost.push_back(1.3 * (double)ents * (double)std::min(P.vsp.tpb, P.nt - x0));
       }
     }
 }
@@ -621,6 +625,11 @@ SweepReq sweep_req(const ReqPlan& P) {
   q.nt = P.nt;
   q.tpc = P.fsp.per_chunk;
   q.epc = P.vsp.per_chunk;
+  q.vsub = P.vsp.sub;
+  q.vtpb = P.vsp.tpb;
+  q.tpx = P.gc.two_pi_over_L[0];
+  q.tpy = P.gc.two_pi_over_L[1];
+  q.tpz = P.gc.two_pi_over_L[2];
   q.kf = P.b.kf;
   q.rec = P.empty ? nullptr : P.ptr<float>(P.o_rec);
   q.fpart = P.need_spec && !P.empty ? P.ptr<float2>(P.o_part) : nullptr;

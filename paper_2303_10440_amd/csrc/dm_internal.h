@@ -43,23 +43,30 @@ struct BandDev {
 constexpr int TRI_REC = 16;
 constexpr float PHASE_GRID = 4096.0f;   // 2^12
 
-// Band-entry record for the VJP sweep: 8 floats (one 32-byte scalar load).
-//  {kx, ky, kz, Wr}, {Wi, xi_x, xi_y, xi_z}
+// Band-entry record of the VJP sweeps: ERC float4 per entry,
+//  {kx, ky, kz, Wr}, {Wi, xi_x, xi_y, xi_z}, {|W|, arg(W) / (2 pi), 0, 0}
+constexpr int ERC = 3;
 
-// Work item of the persistent batched sweep: one 256-wide tile of one
-// request's forward sweep (kind 0: lanes = band entries x0.., triangle chunk c)
-// or gradient sweep (kind 1: lanes = triangles x0.., entry chunk c).
+// Lane-per-entry gradient sweep: VJP_J band entries per lane (entry chunks of
+// 4 waves x 64 lanes x VJP_J entries).
+constexpr int VJP_J = 8;
+constexpr int VJP_CHUNK = 256 * VJP_J;
+
+// Work item of the persistent batched sweep: one tile of one request's
+// forward sweep (kind 0: 256 lanes = band entries x0.., triangle chunk c) or
+// gradient sweep (kind 1: entry chunk c of epc entries, triangles x0.. x0+vtpb).
 struct SweepItem {
   int kind, req, x0, c;
 };
 
 // Per-request pointers and chunking for the batched sweep.
 struct SweepReq {
-  int mode, nE, nt, tpc, epc, pad;
+  int mode, nE, nt, tpc, epc, vsub, vtpb, pad;
+  float tpx, tpy, tpz, pad2;   // 2 pi / L (SURFACE gradient)
   const float4* kf;
   const float* rec;
   float2* fpart;       // [fwd chunks][nE]
-  const float4* erec;  // [nE][2]
+  const float4* erec;  // [nE][ERC]
   float* vpart;        // [vjp chunks][NC][nt]
 };
 
@@ -94,8 +101,13 @@ hipError_t launch_dsig(const GridC& g, BandDev b, const float2* ghat, const floa
 int adjoint_blocks(const GridC& g);
 hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hipStream_t s);
 
-hipError_t launch_vjp_sweep(int mode, const float* tri_rec, int nt, const float4* erec, int64_t nE,
-                            int ents_per_chunk, int n_chunks, float* part, hipStream_t s);
+// Lane-per-entry gradient sweep: n_chunks blocks along the band, each covering
+// chunks_per_block x VJP_CHUNK entries, times triangle chunks of tris_per_block
+// (at most VJP_TPB_MAX); same partial layout [chunk][NC][nt].
+constexpr int VJP_TPB_MAX = 512;
+hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,
+                            int chunks_per_block, int n_chunks, const float4* erec, int64_t nE, float* part,
+                            hipStream_t s);
 int vjp_reduce_groups(int n_chunks);
 hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* tmp, float* red,
                              hipStream_t s);

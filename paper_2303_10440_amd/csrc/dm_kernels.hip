@@ -18,11 +18,12 @@
 // the large part of every phase is reduced exactly before the hardware
 // sine and cosine (v_sin_f32 / v_cos_f32 take revolutions).
 //
-// Work layout: the forward sweep puts one band frequency on each lane and
-// streams triangles as wave-uniform records through the scalar data cache;
-// the VJP sweep puts one triangle on each lane and streams frequencies the
-// same way.  Every reduction is a fixed-order sum (no atomics), so results
-// are bitwise reproducible.
+// Work layout: both sweeps put band frequencies on lanes and stream triangle
+// records as wave-uniform values through the scalar data cache.  The gradient
+// sweep evaluates most pairs in the closed Lagrange form and queues the pairs
+// with nearly coincident nodes in LDS for the stable scheme above, so the
+// stable branch runs on full waves.  Every reduction is a fixed-order sum (no
+// float atomics), so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,6 +38,12 @@ constexpr float PI_F = 3.141592653589793238f;
 constexpr double TWO_PI_D = 6.283185307179586476925286766559;
 // Series branch when the node spread is below one radian.
 constexpr float SERIES_REV = 0.15915494309189535f;   // 1 / (2 pi)
+constexpr float INV_TWO_PI_F = 0.15915494309189535f;
+// Closed (Lagrange) form of the gradient pair when every node gap is at least
+// LAG_GAP revolutions and the spread at least SERIES_REV; other pairs go to
+// vjp_pair.  Its float32 rounding grows like 1 / (2 pi gap)^2, which this gap
+// keeps two orders below the gradient tolerance.
+constexpr float LAG_GAP = 0.02f;
 
 // e^{-2 pi i r} for r in revolutions, r already in [-1/2, 1/2].
 __device__ __forceinline__ void cis_neg(float r, float& c, float& s_neg) {
@@ -228,6 +235,45 @@ __device__ __forceinline__ void vjp_pair(float t1, float d2, float d3, float wr,
   const float v[3] = {0.0f, d2, d3};
 #pragma unroll
   for (int p = 0; p < 3; ++p) z[p] = v[p] == lo ? zl : (v[p] == hi ? zh : zm);
+}
+
+// One gradient pair in closed form (caller checks the gaps, see LAG_GAP).
+// Nodes z_p = -2 pi i t_p with t = (t1, t1 + a, t1 + b); with
+// alpha = 1/(2 pi a), beta = 1/(2 pi b), gamma = 1/(2 pi (b - a)) the divided
+// difference is the Lagrange sum T0 + T1 + T2,
+//   T0 = -alpha beta E0,  T1 = alpha gamma E1,  T2 = -beta gamma E2   (E_p = e^{z_p}),
+// and its derivatives in the nodes (the repeated-node DD4 of Eq. 10) are
+//   DD4_0 = T0 + i[(alpha+beta) T0 + alpha T1 + beta T2]
+//   DD4_1 = T1 + i[(gamma-alpha) T1 - alpha T0 + gamma T2]
+//   DD4_2 = T2 - i[(beta+gamma) T2 + beta T0 + gamma T1].
+// The adjoint weight enters through its modulus and phase, W E_p =
+// |W| e^{-2 pi i (t_p - phi_W)}, so no complex product is formed.
+//   VOLUME:  z[p] = Re(W DD4_p)          SURFACE: wf = Re(W f), z[p] = Im(W DD4_p)
+template <int MODE>
+__device__ __forceinline__ void lag_pair(float t1, float a, float b, float amp, float phw, float& wf, float z[3]) {
+  const float r0 = t1 - phw;
+  const float q0 = wrap(r0), q1 = wrap(r0 + a), q2 = wrap(r0 + b);
+  const float C0 = __builtin_amdgcn_cosf(q0), S0 = -__builtin_amdgcn_sinf(q0);
+  const float C1 = __builtin_amdgcn_cosf(q1), S1 = -__builtin_amdgcn_sinf(q1);
+  const float C2 = __builtin_amdgcn_cosf(q2), S2 = -__builtin_amdgcn_sinf(q2);
+  const float c = b - a;
+  const float ab = a * b;
+  const float rD = __builtin_amdgcn_rcpf(ab * c) * INV_TWO_PI_F;   // 1 / (2 pi a b c)
+  const float al = b * c * rD, be = a * c * rD, ga = ab * rD;
+  const float alw = amp * al;
+  const float k0 = -alw * be, k1 = alw * ga, k2 = -amp * (be * ga);
+  const float R0 = k0 * C0, I0 = k0 * S0, R1 = k1 * C1, I1 = k1 * S1, R2 = k2 * C2, I2 = k2 * S2;
+  const float s01 = al + be, s21 = ga - al, s12 = be + ga;
+  if (MODE == 0) {
+    z[0] = fmaf(-s01, I0, fmaf(-al, I1, fmaf(-be, I2, R0)));
+    z[1] = fmaf(-s21, I1, fmaf(al, I0, fmaf(-ga, I2, R1)));
+    z[2] = fmaf(s12, I2, fmaf(be, I0, fmaf(ga, I1, R2)));
+  } else {
+    wf = R0 + R1 + R2;
+    z[0] = fmaf(s01, R0, fmaf(al, R1, fmaf(be, R2, I0)));
+    z[1] = fmaf(s21, R1, fmaf(-al, R0, fmaf(ga, R2, I1)));
+    z[2] = fmaf(-s12, R2, fmaf(-be, R0, fmaf(-ga, R1, I2)));
+  }
 }
 
 // ------------------------------------------------------------- the band
@@ -627,8 +673,9 @@ __global__ void k_adjoint(GridC g, BandDev b, const float2* __restrict__ ghat, c
     const float a = cp * b.wgt[e] * k.w * g.inv_LV * inv_area;
     const float wr = a * (G.x * pr + G.y * pi);
     const float wi = a * (G.x * pi - G.y * pr);
-    erec[2 * e] = make_float4(k.x, k.y, k.z, wr);
-    erec[2 * e + 1] = make_float4(wi, k.x * g.two_pi_over_L[0], k.y * g.two_pi_over_L[1], k.z * g.two_pi_over_L[2]);
+    erec[ERC * e] = make_float4(k.x, k.y, k.z, wr);
+    erec[ERC * e + 1] = make_float4(wi, k.x * g.two_pi_over_L[0], k.y * g.two_pi_over_L[1], k.z * g.two_pi_over_L[2]);
+    erec[ERC * e + 2] = make_float4(sqrtf(fmaf(wr, wr, wi * wi)), atan2f(wi, wr) * INV_TWO_PI_F, 0.0f, 0.0f);
   }
 }
 
@@ -685,58 +732,148 @@ __global__ void __launch_bounds__(64) k_dsig_final(const double* __restrict__ pa
 }
 
 // --------------------------------------------------------------- VJP sweep
-// Gradient sweep over one tile: lane = triangle t, band entries [e0, e1).
-// Writes NC channels to part[j * nt + t] (channel-major rows of one chunk).
+// Lane-per-entry gradient sweep.  A block owns n_sub consecutive entry chunks
+// of VJP_CHUNK band entries (in chunk g: wave w, step j, lane l -> entry
+// 64 (w VJP_J + j) + l) and a range of at most VJP_TPB_MAX triangles, which are
+// wave-uniform.  Pairs whose nodes are too close for the closed form are
+// queued in LDS and evaluated by vjp_pair after each triangle, so the stable
+// branch runs on full waves instead of diverging.  Per triangle the lane sums
+// are reduced over the wave (butterfly, lane 0's order), over the 4 waves and
+// then over the entry chunks, each in a fixed order, into part_out[NC][nt].
+constexpr int VJP_TB = 32;   // triangles between block-level merges
+
+struct VjpLds {
+  uint16_t queue[4][64 * VJP_J];
+  float tot[4][VJP_TB][10];
+  float sum[VJP_TPB_MAX][10];
+};
+
 template <int MODE>
-__device__ __forceinline__ void vjp_tile(const float* __restrict__ rec, int nt, const float4* __restrict__ erec,
-                                         int e0, int e1, int t, float* __restrict__ part) {
+__device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, int nt, int t0, int t1,
+                                               const float4* __restrict__ erec, int64_t nE, int64_t e_begin,
+                                               int n_sub, float tpx, float tpy, float tpz,
+                                               float* __restrict__ part_out, VjpLds& L) {
   constexpr int NC = MODE == 0 ? 3 : 10;
-  float r[12];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int g = 0; g < n_sub; ++g) {
+    const int64_t ew = e_begin + (int64_t)g * VJP_CHUNK + (int64_t)w * 64 * VJP_J;
+    float kx[VJP_J], ky[VJP_J], kz[VJP_J], amp[VJP_J], phw[VJP_J];
+    uint32_t vm = 0;
 #pragma unroll
-  for (int j = 0; j < 12; ++j) r[j] = 0.0f;
-  if (t < nt) {
-    const float4* rr = reinterpret_cast<const float4*>(rec + (size_t)t * TRI_REC);
-    const float4 a = rr[0], bq = rr[1], c = rr[2];
-    r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
-    r[4] = bq.x; r[5] = bq.y; r[6] = bq.z; r[7] = bq.w;
-    r[8] = c.x; r[9] = c.y; r[10] = c.z; r[11] = c.w;
-  }
-  float acc[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) acc[j] = 0.0f;
-  for (int e = e0; e < e1; ++e) {
-    const float4 A = erec[2 * e], B = erec[2 * e + 1];
-    float tv, d2, d3;
-    tri_phases(A.x, A.y, A.z, r, tv, d2, d3);
-    float wf = 0.0f, z[3];
-    vjp_pair<MODE>(tv, d2, d3, A.w, B.x, wf, z);
-    if (MODE == 0) {
-#pragma unroll
-      for (int p = 0; p < 3; ++p) acc[p] += z[p];
-    } else {
-      acc[0] += wf;
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        acc[1 + 3 * p] = fmaf(z[p], B.y, acc[1 + 3 * p]);
-        acc[2 + 3 * p] = fmaf(z[p], B.z, acc[2 + 3 * p]);
-        acc[3 + 3 * p] = fmaf(z[p], B.w, acc[3 + 3 * p]);
+    for (int j = 0; j < VJP_J; ++j) {
+      const int64_t e = ew + 64 * j + lane;
+      kx[j] = ky[j] = kz[j] = amp[j] = phw[j] = 0.0f;
+      if (e < nE) {
+        const float4 A = erec[ERC * e], C = erec[ERC * e + 2];
+        kx[j] = A.x;
+        ky[j] = A.y;
+        kz[j] = A.z;
+        amp[j] = C.x;
+        phw[j] = C.y;
+        vm |= 1u << j;
       }
     }
-  }
-  if (t < nt) {
+    for (int tb = t0; tb < t1; tb += VJP_TB) {
+      const int tn = min(VJP_TB, t1 - tb);
+      for (int tt = 0; tt < tn; ++tt) {
+        const float* r = rec + (size_t)(tb + tt) * TRI_REC;
+        float acc[NC];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) part[(size_t)j * nt + t] = acc[j];
+        for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
+        int nq = 0;
+#pragma unroll
+        for (int j = 0; j < VJP_J; ++j) {
+          float tv, a, b;
+          tri_phases(kx[j], ky[j], kz[j], r, tv, a, b);
+          const float c = b - a;
+          const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
+          const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
+          const bool fast = mn >= LAG_GAP && mx >= SERIES_REV;
+          float wf = 0.0f, z[3];
+          lag_pair<MODE>(tv, a, b, amp[j], phw[j], wf, z);
+          if (MODE == 0) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) acc[p] += fast ? z[p] : 0.0f;
+          } else {
+            const float x0 = kx[j] * tpx, x1 = ky[j] * tpy, x2 = kz[j] * tpz;
+            acc[0] += fast ? wf : 0.0f;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+              const float zp = fast ? z[p] : 0.0f;
+              acc[1 + 3 * p] = fmaf(zp, x0, acc[1 + 3 * p]);
+              acc[2 + 3 * p] = fmaf(zp, x1, acc[2 + 3 * p]);
+              acc[3 + 3 * p] = fmaf(zp, x2, acc[3 + 3 * p]);
+            }
+          }
+          const bool need = !fast && ((vm >> j) & 1u);
+          const uint64_t bal = __ballot(need);
+          if (need) {
+            const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            L.queue[w][pos] = (uint16_t)((j << 6) | lane);
+          }
+          nq += __popcll(bal);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q0 = 0; q0 < nq; q0 += 64) {
+          if (q0 + lane < nq) {
+            const int it = L.queue[w][q0 + lane];
+            const int64_t e = ew + 64 * (it >> 6) + (it & 63);
+            const float4 A = erec[ERC * e], B = erec[ERC * e + 1];
+            float tv, a, b, wf = 0.0f, z[3];
+            tri_phases(A.x, A.y, A.z, r, tv, a, b);
+            vjp_pair<MODE>(tv, a, b, A.w, B.x, wf, z);
+            if (MODE == 0) {
+#pragma unroll
+              for (int p = 0; p < 3; ++p) acc[p] += z[p];
+            } else {
+              acc[0] += wf;
+#pragma unroll
+              for (int p = 0; p < 3; ++p) {
+                acc[1 + 3 * p] = fmaf(z[p], B.y, acc[1 + 3 * p]);
+                acc[2 + 3 * p] = fmaf(z[p], B.z, acc[2 + 3 * p]);
+                acc[3 + 3 * p] = fmaf(z[p], B.w, acc[3 + 3 * p]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) {
+          float v = acc[ch];
+#pragma unroll
+          for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+          if (lane == 0) L.tot[w][tt][ch] = v;
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < tn * NC; i += SWEEP_T) {
+        const int tt = i / NC, ch = i - tt * NC;
+        const float v = (L.tot[0][tt][ch] + L.tot[1][tt][ch]) + (L.tot[2][tt][ch] + L.tot[3][tt][ch]);
+        float& acc_t = L.sum[tb - t0 + tt][ch];
+        acc_t = g == 0 ? v : acc_t + v;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < (t1 - t0) * NC; i += SWEEP_T) {
+    const int tl = i / NC, ch = i - tl * NC;
+    part_out[(size_t)ch * nt + t0 + tl] = n_sub > 0 ? L.sum[tl][ch] : 0.0f;
   }
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_vjp_sweep(const float* __restrict__ rec, int nt,
-                                                         const float4* __restrict__ erec, int nE, int epc,
+__global__ void __launch_bounds__(SWEEP_T) k_vjp_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb,
+                                                         const float4* __restrict__ erec, int64_t nE, int n_sub,
                                                          float* __restrict__ part) {
+  __shared__ VjpLds L;
   constexpr int NC = MODE == 0 ? 3 : 10;
-  const int e0 = blockIdx.y * epc;
-  vjp_tile<MODE>(rec, nt, erec, e0, min(nE, e0 + epc), blockIdx.x * SWEEP_T + threadIdx.x,
-                 part + (size_t)blockIdx.y * NC * nt);
+  const int t0 = blockIdx.y * tpb;
+  const int64_t e_begin = (int64_t)blockIdx.x * n_sub * VJP_CHUNK;
+  const int sub = (int)min<int64_t>(n_sub, (nE - e_begin + VJP_CHUNK - 1) / VJP_CHUNK);
+  vjp_lanes_tile<MODE>(rec, nt, t0, min(nt, t0 + tpb), erec, nE, e_begin, sub, g.two_pi_over_L[0],
+                       g.two_pi_over_L[1], g.two_pi_over_L[2], part + (size_t)blockIdx.x * NC * nt, L);
 }
 
 // Persistent sweep over a list of work items from many independent meshes
@@ -747,6 +884,7 @@ __global__ void __launch_bounds__(SWEEP_T) k_batch_sweep(const SweepItem* __rest
                                                            const SweepReq* __restrict__ reqs,
                                                            int* __restrict__ counter) {
   __shared__ int slot;
+  __shared__ VjpLds L;
   for (;;) {
     if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
     __syncthreads();
@@ -755,8 +893,8 @@ __global__ void __launch_bounds__(SWEEP_T) k_batch_sweep(const SweepItem* __rest
     if (it >= n_items) return;
     const SweepItem w = items[it];
     const SweepReq q = reqs[w.req];
-    const int lane = w.x0 + (int)threadIdx.x;
     if (w.kind == 0) {
+      const int lane = w.x0 + (int)threadIdx.x;
       const int t0 = w.c * q.tpc, t1 = min(q.nt, t0 + q.tpc);
       float2* row = q.fpart + (size_t)w.c * q.nE;
       if (q.mode == 0)
@@ -764,11 +902,15 @@ __global__ void __launch_bounds__(SWEEP_T) k_batch_sweep(const SweepItem* __rest
       else
         fwd_tile<1>(q.kf, q.nE, q.rec, t0, t1, lane, row);
     } else {
-      const int e0 = w.c * q.epc, e1 = min(q.nE, e0 + q.epc);
+      const int64_t e_begin = (int64_t)w.c * q.epc;
+      const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + VJP_CHUNK - 1) / VJP_CHUNK);
+      const int t1 = min(q.nt, w.x0 + q.vtpb);
       if (q.mode == 0)
-        vjp_tile<0>(q.rec, q.nt, q.erec, e0, e1, lane, q.vpart + (size_t)w.c * 3 * q.nt);
+        vjp_lanes_tile<0>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
+                          q.vpart + (size_t)w.c * 3 * q.nt, L);
       else
-        vjp_tile<1>(q.rec, q.nt, q.erec, e0, e1, lane, q.vpart + (size_t)w.c * 10 * q.nt);
+        vjp_lanes_tile<1>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
+                          q.vpart + (size_t)w.c * 10 * q.nt, L);
     }
   }
 }
@@ -987,13 +1129,19 @@ hipError_t launch_batch_sweep(const SweepItem* items, int n_items, const SweepRe
   return hipGetLastError();
 }
 
-hipError_t launch_vjp_sweep(int mode, const float* tri_rec, int nt, const float4* erec, int64_t nE,
-                            int ents_per_chunk, int n_chunks, float* part, hipStream_t s) {
-  const dim3 grid(blocks_for(nt, SWEEP_T), (unsigned)n_chunks);
+hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,
+                            int chunks_per_block, int n_chunks, const float4* erec, int64_t nE, float* part,
+                            hipStream_t s) {
+  if (tris_per_block < 1 || tris_per_block > VJP_TPB_MAX || chunks_per_block < 1 ||
+      (int64_t)n_chunks * chunks_per_block * VJP_CHUNK < nE)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)n_chunks, blocks_for(nt, tris_per_block));
   if (mode == 0)
-    hipLaunchKernelGGL(k_vjp_sweep<0>, grid, dim3(SWEEP_T), 0, s, tri_rec, nt, erec, (int)nE, ents_per_chunk, part);
+    hipLaunchKernelGGL(k_vjp_lanes<0>, grid, dim3(SWEEP_T), 0, s, g, tri_rec, nt, tris_per_block, erec, nE,
+                       chunks_per_block, part);
   else
-    hipLaunchKernelGGL(k_vjp_sweep<1>, grid, dim3(SWEEP_T), 0, s, tri_rec, nt, erec, (int)nE, ents_per_chunk, part);
+    hipLaunchKernelGGL(k_vjp_lanes<1>, grid, dim3(SWEEP_T), 0, s, g, tri_rec, nt, tris_per_block, erec, nE,
+                       chunks_per_block, part);
   return hipGetLastError();
 }
 
