@@ -507,7 +507,9 @@ SweepPlan plan_fwd_batch(int64_t nE, int nt) {
 
 SweepPlan plan_vjp_batch(int64_t nE, int nt) {
   SweepPlan sp = plan_vjp(nE, nt);
-  sp.tpb = std::max(1, std::min(nt, VJP_TPB_MAX));
+  int tpb = 32;   // about 2^20 pairs per gradient item
+  while (tpb < VJP_TPB_MAX && (int64_t)2 * tpb * sp.per_chunk <= ((int64_t)1 << 20)) tpb *= 2;
+  sp.tpb = std::max(1, std::min(nt, tpb));
   return sp;
 }
 
@@ -712,8 +714,9 @@ void fill_plan(ReqPlan& P, const dm_request& r) {
 // per-request sweep descriptors and the queue counter.
 struct BatchLayout {
   std::vector<size_t> off;
-  std::vector<SweepItem> items;   // longest first
+  std::vector<SweepItem> items;   // forward items, then gradient items, each longest first
   std::vector<SweepReq> reqs;
+  int n_fwd = 0;
   size_t o_items = 0, o_reqs = 0, o_counter = 0, total = 0;
   double pairs = 0.0;
 };
@@ -733,9 +736,16 @@ void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
   }
   std::vector<size_t> order(items.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    if (items[a].kind != items[b].kind) return items[a].kind < items[b].kind;
+    return cost[a] > cost[b];
+  });
   L.items.resize(items.size());
-  for (size_t i = 0; i < order.size(); ++i) L.items[i] = items[order[i]];
+  L.n_fwd = 0;
+  for (size_t i = 0; i < order.size(); ++i) {
+    L.items[i] = items[order[i]];
+    L.n_fwd += L.items[i].kind == 0 ? 1 : 0;
+  }
   L.o_items = L.total;
   L.total += align_up(std::max<size_t>(1, L.items.size()) * sizeof(SweepItem));
   L.o_reqs = L.total;
@@ -756,11 +766,10 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
     HIP_TRY(hipMemcpyAsync(base + L.o_items, L.items.data(), L.items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
                            s));
     HIP_TRY(hipMemcpyAsync(base + L.o_reqs, L.reqs.data(), n * sizeof(SweepReq), hipMemcpyHostToDevice, s));
-    const int blocks = (int)std::min<size_t>(L.items.size(), 2048);
     SweepTimer tm(h, s, 2, L.pairs);
-    HIP_TRY(launch_batch_sweep(reinterpret_cast<const SweepItem*>(base + L.o_items), (int)L.items.size(),
+    HIP_TRY(launch_batch_sweep(reinterpret_cast<const SweepItem*>(base + L.o_items), L.n_fwd, (int)L.items.size(),
                                reinterpret_cast<const SweepReq*>(base + L.o_reqs),
-                               reinterpret_cast<int*>(base + L.o_counter), blocks, s));
+                               reinterpret_cast<int*>(base + L.o_counter), s));
     tm.done();
   }
   for (size_t i = 0; i < n; ++i) DM_TRY(stage_post(h, P[i], s));

@@ -73,7 +73,9 @@ struct SweepReq {
 constexpr int SWEEP_THREADS = 256;
 
 // ---- launchers (defined in dm_kernels.hip); all enqueue on `s` ----
-hipError_t launch_batch_sweep(const SweepItem* items, int n_items, const SweepReq* reqs, int* counter, int blocks,
+// Two persistent launches: forward items [0, n_fwd), gradient items
+// [n_fwd, n_items); counters[0..1] are zeroed first.
+hipError_t launch_batch_sweep(const SweepItem* items, int n_fwd, int n_items, const SweepReq* reqs, int* counters,
                               hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_band_count(const GridC& g, const double* sigma6, double qmax, int32_t* cnt, int64_t n_slots,

@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "dm_internal.h"
 
 namespace dm {
@@ -876,42 +878,56 @@ __global__ void __launch_bounds__(SWEEP_T) k_vjp_lanes(GridC g, const float* __r
                        g.two_pi_over_L[1], g.two_pi_over_L[2], part + (size_t)blockIdx.x * NC * nt, L);
 }
 
-// Persistent sweep over a list of work items from many independent meshes
-// (forward and gradient tiles alike).  Each workgroup takes the next item from
-// a global counter; every item writes its own partial slot, so the results do
-// not depend on which workgroup ran which item.
-__global__ void __launch_bounds__(SWEEP_T) k_batch_sweep(const SweepItem* __restrict__ items, int n_items,
-                                                           const SweepReq* __restrict__ reqs,
-                                                           int* __restrict__ counter) {
+// Persistent sweeps over the work items of many independent meshes: one
+// launch for the forward tiles, one for the gradient tiles (their register
+// and LDS footprints differ, so each runs at its own occupancy).  Each
+// workgroup takes the next item from a global counter; every item writes its
+// own partial slot, so the results do not depend on which workgroup ran which
+// item.
+__device__ __forceinline__ int next_item(int* counter, int* slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+  __syncthreads();
+  const int it = __builtin_amdgcn_readfirstlane(*slot);
+  __syncthreads();
+  return it;
+}
+
+__global__ void __launch_bounds__(SWEEP_T) k_batch_fwd(const SweepItem* __restrict__ items, int n_items,
+                                                         const SweepReq* __restrict__ reqs, int* __restrict__ counter) {
   __shared__ int slot;
-  __shared__ VjpLds L;
   for (;;) {
-    if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(slot);
-    __syncthreads();
+    const int it = next_item(counter, &slot);
     if (it >= n_items) return;
     const SweepItem w = items[it];
     const SweepReq q = reqs[w.req];
-    if (w.kind == 0) {
-      const int lane = w.x0 + (int)threadIdx.x;
-      const int t0 = w.c * q.tpc, t1 = min(q.nt, t0 + q.tpc);
-      float2* row = q.fpart + (size_t)w.c * q.nE;
-      if (q.mode == 0)
-        fwd_tile<0>(q.kf, q.nE, q.rec, t0, t1, lane, row);
-      else
-        fwd_tile<1>(q.kf, q.nE, q.rec, t0, t1, lane, row);
-    } else {
-      const int64_t e_begin = (int64_t)w.c * q.epc;
-      const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + VJP_CHUNK - 1) / VJP_CHUNK);
-      const int t1 = min(q.nt, w.x0 + q.vtpb);
-      if (q.mode == 0)
-        vjp_lanes_tile<0>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
-                          q.vpart + (size_t)w.c * 3 * q.nt, L);
-      else
-        vjp_lanes_tile<1>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
-                          q.vpart + (size_t)w.c * 10 * q.nt, L);
-    }
+    const int lane = w.x0 + (int)threadIdx.x;
+    const int t0 = w.c * q.tpc, t1 = min(q.nt, t0 + q.tpc);
+    float2* row = q.fpart + (size_t)w.c * q.nE;
+    if (q.mode == 0)
+      fwd_tile<0>(q.kf, q.nE, q.rec, t0, t1, lane, row);
+    else
+      fwd_tile<1>(q.kf, q.nE, q.rec, t0, t1, lane, row);
+  }
+}
+
+__global__ void __launch_bounds__(SWEEP_T) k_batch_vjp(const SweepItem* __restrict__ items, int n_items,
+                                                         const SweepReq* __restrict__ reqs, int* __restrict__ counter) {
+  __shared__ int slot;
+  __shared__ VjpLds L;
+  for (;;) {
+    const int it = next_item(counter, &slot);
+    if (it >= n_items) return;
+    const SweepItem w = items[it];
+    const SweepReq q = reqs[w.req];
+    const int64_t e_begin = (int64_t)w.c * q.epc;
+    const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + VJP_CHUNK - 1) / VJP_CHUNK);
+    const int t1 = min(q.nt, w.x0 + q.vtpb);
+    if (q.mode == 0)
+      vjp_lanes_tile<0>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
+                        q.vpart + (size_t)w.c * 3 * q.nt, L);
+    else
+      vjp_lanes_tile<1>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
+                        q.vpart + (size_t)w.c * 10 * q.nt, L);
   }
 }
 
@@ -1122,10 +1138,15 @@ hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hip
   return hipGetLastError();
 }
 
-hipError_t launch_batch_sweep(const SweepItem* items, int n_items, const SweepReq* reqs, int* counter, int blocks,
+hipError_t launch_batch_sweep(const SweepItem* items, int n_fwd, int n_items, const SweepReq* reqs, int* counters,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(counter), (int64_t)1);
-  hipLaunchKernelGGL(k_batch_sweep, dim3((unsigned)blocks), dim3(SWEEP_T), 0, s, items, n_items, reqs, counter);
+  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(counters), (int64_t)2);
+  if (n_fwd > 0)
+    hipLaunchKernelGGL(k_batch_fwd, dim3((unsigned)std::min(n_fwd, 2048)), dim3(SWEEP_T), 0, s, items, n_fwd, reqs,
+                       counters);
+  if (n_items > n_fwd)
+    hipLaunchKernelGGL(k_batch_vjp, dim3((unsigned)std::min(n_items - n_fwd, 1280)), dim3(SWEEP_T), 0, s,
+                       items + n_fwd, n_items - n_fwd, reqs, counters + 1);
   return hipGetLastError();
 }
 
