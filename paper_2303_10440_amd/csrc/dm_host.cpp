@@ -127,12 +127,16 @@ struct dm_handle {
   dm_kernel_time acc[3] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}, {0, 0.0, 0.0}};
 };
 
+// Triangles are kept in strip order: consecutive triangles of a strip share
+// an edge, triangle i of a strip is (s_i, s_i+1, s_i+2), so each one brings a
+// single new vertex (the sweeps reuse the other two vertex phases).
 struct dm_topology {
   dm_handle* h = nullptr;
-  int nt = 0, nv = 0, closed = 0;
-  int32_t* faces = nullptr;     // device [nt][3]
+  int nt = 0, nv = 0, closed = 0, n_strips = 0;
+  int32_t* faces = nullptr;     // device [nt][3], strip order
   int32_t* csr_off = nullptr;   // device [nv+1]
-  int32_t* csr_ent = nullptr;   // device [3 nt] = 3 t + p
+  int32_t* csr_ent = nullptr;   // device [3 nt] = 3 t + p (strip-order t, p)
+  int32_t* flags = nullptr;     // device [nt]: TRI_STRIP_START, TRI_REVERSED
   size_t bytes = 0;
 };
 
@@ -377,22 +381,99 @@ dm_status check_mesh(const dm_mesh* m, int mode) {
   return DM_OK;
 }
 
+// Greedy triangle strips.  From each unused seed triangle (in input order)
+// the strip is grown across the edge formed by its last two vertices while the
+// triangle across it is unused; of the seed's three rotations the longest
+// strip is kept.  Output: faces in strip order (s_i, s_i+1, s_i+2) and flags
+// (strip start; odd permutation of the input face, i.e. reversed orientation).
+int build_strips(const std::vector<int32_t>& F, std::vector<int32_t>& Fs, std::vector<int32_t>& flags) {
+  const int nt = (int)(F.size() / 3);
+  std::vector<std::pair<uint64_t, int>> edges;
+  edges.reserve(F.size());
+  for (int t = 0; t < nt; ++t)
+    for (int p = 0; p < 3; ++p) {
+      const uint32_t a = (uint32_t)F[3 * t + p], b = (uint32_t)F[3 * t + (p + 1) % 3];
+      edges.push_back({((uint64_t)std::min(a, b) << 32) | std::max(a, b), t});
+    }
+  std::sort(edges.begin(), edges.end());
+  std::vector<char> used((size_t)nt, 0), trial((size_t)nt, 0);
+  // the unused triangle other than `from` across edge {x, y}, or -1
+  auto across = [&](int32_t x, int32_t y, const std::vector<char>& taken) {
+    const uint64_t key = ((uint64_t)std::min((uint32_t)x, (uint32_t)y) << 32) | std::max((uint32_t)x, (uint32_t)y);
+    auto it = std::lower_bound(edges.begin(), edges.end(), std::make_pair(key, -1));
+    for (; it != edges.end() && it->first == key; ++it)
+      if (!used[(size_t)it->second] && !taken[(size_t)it->second]) return it->second;
+    return -1;
+  };
+  auto third = [&](int u, int32_t x, int32_t y) {
+    for (int p = 0; p < 3; ++p) {
+      const int32_t z = F[3 * u + p];
+      if (z != x && z != y) return z;
+    }
+    return F[3 * u];
+  };
+  Fs.clear();
+  flags.clear();
+  Fs.reserve(F.size());
+  flags.reserve((size_t)nt);
+  int n_strips = 0;
+  std::vector<int> tris, best_tris;
+  std::vector<int32_t> seq, best_seq;
+  for (int s = 0; s < nt; ++s) {
+    if (used[(size_t)s]) continue;
+    best_tris.clear();
+    for (int r = 0; r < 3; ++r) {
+      seq = {F[3 * s + r], F[3 * s + (r + 1) % 3], F[3 * s + (r + 2) % 3]};
+      tris = {s};
+      trial[(size_t)s] = 1;
+      for (;;) {
+        const int32_t x = seq[seq.size() - 2], y = seq.back();
+        const int u = across(x, y, trial);
+        if (u < 0) break;
+        trial[(size_t)u] = 1;
+        tris.push_back(u);
+        seq.push_back(third(u, x, y));
+      }
+      for (int u : tris) trial[(size_t)u] = 0;
+      if (tris.size() > best_tris.size()) {
+        best_tris = tris;
+        best_seq = seq;
+      }
+    }
+    for (size_t i = 0; i < best_tris.size(); ++i) {
+      const int u = best_tris[i];
+      used[(size_t)u] = 1;
+      const int32_t a = best_seq[i], b = best_seq[i + 1], c = best_seq[i + 2];
+      Fs.push_back(a);
+      Fs.push_back(b);
+      Fs.push_back(c);
+      // (a, b, c) is a rotation of the input face (same orientation) or not
+      bool same = false;
+      for (int r = 0; r < 3; ++r)
+        same = same || (F[3 * u + r] == a && F[3 * u + (r + 1) % 3] == b && F[3 * u + (r + 2) % 3] == c);
+      flags.push_back((i == 0 ? TRI_STRIP_START : 0) | (same ? 0 : TRI_REVERSED));
+    }
+    ++n_strips;
+  }
+  return n_strips;
+}
+
 // Launch geometry of the two sweeps.
 struct SweepPlan {
   int n_chunks = 1, per_chunk = 1;
   int sub = 1, tpb = 1;   // lane-per-entry gradient sweep: entry chunks per block, triangles per block
 };
 
+// Forward sweep (band entries on lanes): blocks of FWD_CHUNK entries times
+// triangle chunks, about 2560 blocks in all, chunks of at least 64 triangles.
 SweepPlan plan_fwd(int64_t nE, int nt) {
   SweepPlan sp;
-  const int64_t tiles = (nE + 255) / 256;
-  int64_t want = (16384 + tiles - 1) / std::max<int64_t>(tiles, 1);
-  const int64_t maxc = std::max<int64_t>(1, nt / 32);
-  sp.n_chunks = (int)std::max<int64_t>(1, std::min(want, maxc));
-  sp.per_chunk = (int)((nt + sp.n_chunks - 1) / sp.n_chunks);
-  if (sp.per_chunk < 1) sp.per_chunk = 1;
-  sp.n_chunks = (int)((nt + sp.per_chunk - 1) / sp.per_chunk);
-  if (sp.n_chunks < 1) sp.n_chunks = 1;
+  const int64_t eblocks = std::max<int64_t>(1, (nE + FWD_CHUNK - 1) / FWD_CHUNK);
+  const int64_t want = (2560 + eblocks - 1) / eblocks;
+  const int64_t most = std::max<int64_t>(1, nt / 64);
+  sp.n_chunks = (int)std::max<int64_t>(1, std::min(want, most));
+  sp.per_chunk = std::max(1, (nt + sp.n_chunks - 1) / sp.n_chunks);
+  sp.n_chunks = std::max(1, (nt + sp.per_chunk - 1) / sp.per_chunk);
   return sp;
 }
 
@@ -568,7 +649,7 @@ dm_status stage_pre(dm_handle* h, ReqPlan& P, hipStream_t s) {
     DM_TRY(zero_fill(P.dS, 6, s));
     return DM_OK;
   }
-  HIP_TRY(launch_mesh_prep(P.mode, P.gc, P.m->verts_dev, P.nv, P.m->topo->faces, P.nt, P.ptr<float>(P.o_rec),
+  HIP_TRY(launch_mesh_prep(P.mode, P.gc, P.m->verts_dev, P.nv, P.m->topo->faces, P.m->topo->flags, P.nt, P.ptr<float>(P.o_rec),
                            P.ptr<MeshInfo>(P.o_info), P.ptr<double>(P.o_ptmp), P.prep_blocks, s));
   if (P.want_vjp) {
     HIP_TRY(hipMemcpyAsync(P.ptr<float>(P.o_gin), P.dLdI, (size_t)P.nvox * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -586,7 +667,7 @@ dm_status stage_sweeps(dm_handle* h, ReqPlan& P, hipStream_t s) {
   if (P.empty) return DM_OK;
   if (P.need_spec) {
     SweepTimer tm(h, s, 0, (double)P.nE * P.nt);
-    HIP_TRY(launch_fwd_sweep(P.mode, P.b.kf, P.nE, P.ptr<float>(P.o_rec), P.nt, P.fsp.per_chunk, P.fsp.n_chunks,
+    HIP_TRY(launch_fwd_lanes(P.mode, P.b.kf, P.nE, P.ptr<float>(P.o_rec), P.nt, P.fsp.per_chunk, P.fsp.n_chunks,
                              P.ptr<float2>(P.o_part), s));
     tm.done();
   }
@@ -605,9 +686,9 @@ void add_items(const ReqPlan& P, int req, std::vector<SweepItem>& items, std::ve
   if (P.need_spec)
     for (int c = 0; c < P.fsp.n_chunks; ++c) {
       const int tris = std::min(P.nt, (c + 1) * P.fsp.per_chunk) - c * P.fsp.per_chunk;
-      for (int64_t x0 = 0; x0 < P.nE; x0 += SWEEP_THREADS) {
+      for (int64_t x0 = 0; x0 < P.nE; x0 += FWD_CHUNK) {
         items.push_back({0, req, (int)x0, c});
-        cost.push_back((double)tris * (double)std::min<int64_t>(SWEEP_THREADS, P.nE - x0));
+        cost.push_back((double)tris * (double)std::min<int64_t>(FWD_CHUNK, P.nE - x0));
       }
     }
   if (P.want_vjp && P.dV)
@@ -662,7 +743,7 @@ dm_status stage_post(dm_handle* h, ReqPlan& P, hipStream_t s) {
     HIP_TRY(launch_vjp_reduce(P.mode, P.ptr<float>(P.o_vpart), P.vsp.n_chunks, P.nt, P.ptr<float>(P.o_rtmp), red, s));
     double* R = P.ptr<double>(P.o_R);
     if (P.mode == DM_SURFACE) HIP_TRY(launch_surface_scalar(red, P.ptr<float>(P.o_rec), P.nt, info, R, s));
-    HIP_TRY(launch_vertex_gather(P.mode, P.m->verts_dev, P.nv, P.m->topo->faces, P.nt, P.m->topo->csr_off,
+    HIP_TRY(launch_vertex_gather(P.mode, P.m->verts_dev, P.nv, P.m->topo->faces, P.m->topo->flags, P.nt, P.m->topo->csr_off,
                                  P.m->topo->csr_ent, red, R, P.dV, s));
   }
   return DM_OK;
@@ -900,6 +981,9 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
         break;
       }
     }
+  std::vector<int32_t> Fs, fl;
+  const int n_strips = build_strips(F, Fs, fl);
+  F.swap(Fs);
   // vertex incidence (CSR)
   std::vector<int32_t> off((size_t)n_verts + 1, 0), ent(F.size());
   for (size_t i = 0; i < F.size(); ++i) off[(size_t)F[i] + 1]++;
@@ -911,17 +995,21 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
   t->nt = n_faces;
   t->nv = n_verts;
   t->closed = closed ? 1 : 0;
-  const size_t bf = align_up(F.size() * 4), bo = align_up(off.size() * 4), be = align_up(ent.size() * 4);
+  t->n_strips = n_strips;
+  const size_t bf = align_up(F.size() * 4), bo = align_up(off.size() * 4), be = align_up(ent.size() * 4),
+               bl = align_up(fl.size() * 4);
   void* mem = nullptr;
-  DM_TRY(dev_alloc(h, &mem, bf + bo + be));
-  t->bytes = bf + bo + be;
+  DM_TRY(dev_alloc(h, &mem, bf + bo + be + bl));
+  t->bytes = bf + bo + be + bl;
   t->faces = static_cast<int32_t*>(mem);
   t->csr_off = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf);
   t->csr_ent = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo);
+  t->flags = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be);
   hipError_t err = hipSuccess;
   if (!F.empty()) err = hipMemcpy(t->faces, F.data(), F.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemcpy(t->csr_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess && !ent.empty()) err = hipMemcpy(t->csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
+  if (err == hipSuccess && !fl.empty()) err = hipMemcpy(t->flags, fl.data(), fl.size() * 4, hipMemcpyHostToDevice);
   if (err != hipSuccess) {
     dev_free(h, mem, t->bytes);
     return fail(DM_ERR_DEVICE, "topology upload: %s", hipGetErrorString(err));
@@ -1084,13 +1172,13 @@ dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g,
   DM_TRY(ensure_ws(h, cv.off));
   float* rec = at<float>(h, o_rec);
   MeshInfo* info = at<MeshInfo>(h, o_info);
-  HIP_TRY(launch_mesh_prep(mode, gc, mesh->verts_dev, mesh->n_verts, mesh->topo->faces, nt, rec, info,
+  HIP_TRY(launch_mesh_prep(mode, gc, mesh->verts_dev, mesh->n_verts, mesh->topo->faces, mesh->topo->flags, nt, rec, info,
                            at<double>(h, o_ptmp), prep_blocks, s));
   float4* kf = at<float4>(h, o_kf);
   HIP_TRY(launch_points_prepare(gc, k_dev, n, kf, s));
   float2* part = at<float2>(h, o_part);
   SweepTimer tm(h, s, 0, (double)n * nt);
-  HIP_TRY(launch_fwd_sweep(mode, kf, n, rec, nt, sp.per_chunk, sp.n_chunks, part, s));
+  HIP_TRY(launch_fwd_lanes(mode, kf, n, rec, nt, sp.per_chunk, sp.n_chunks, part, s));
   tm.done();
   HIP_TRY(launch_points_finalize(mode, gc, kf, n, part, sp.n_chunks, info, reinterpret_cast<float2*>(out_dev), s));
   return end_call(h, s);

@@ -35,12 +35,16 @@ struct BandDev {
   int32_t* map;            // [n_pos] first entry | (count-1) << 30, or -1
 };
 
-// Triangle record for the sweeps: 16 floats (one 64-byte scalar load).
-//  [0..2] u1_hi, [3..5] u1_lo : (v1 - c)/L split into a 12-bit grid part and rest
+// Triangle record for the sweeps: 16 floats (one 64-byte scalar load), for
+// the triangle (v1, v2, v3) in strip order (v3 is the vertex it adds).
+//  [0..2] u3_hi, [3..5] u3_lo : (v3 - c)/L split into a 12-bit grid part and rest
 //  [6..8] e2 = (v2 - v1)/L,  [9..11] e3 = (v3 - v1)/L
-//  [12..14] VOLUME: n_T / L (n_T = (v2-v1)x(v3-v1));  SURFACE: [12] = 2 A_T
-//  [15] unused
+//  [12..14] VOLUME: n_T / L, n_T the outward (v2-v1)x(v3-v1);  SURFACE: [12] = 2 A_T
+//  [15] 1 for the first triangle of a strip, else 0
 constexpr int TRI_REC = 16;
+// Per-triangle flags of the strip order.
+constexpr int TRI_STRIP_START = 1;   // first triangle of a strip
+constexpr int TRI_REVERSED = 2;      // strip order is an odd permutation of the input face
 constexpr float PHASE_GRID = 4096.0f;   // 2^12
 
 // Band-entry record of the VJP sweeps: ERC float4 per entry,
@@ -51,9 +55,12 @@ constexpr int ERC = 3;
 // 4 waves x 64 lanes x VJP_J entries).
 constexpr int VJP_J = 8;
 constexpr int VJP_CHUNK = 256 * VJP_J;
+// Forward sweep: FWD_J band entries per lane, FWD_CHUNK entries per block.
+constexpr int FWD_J = 4;
+constexpr int FWD_CHUNK = 256 * FWD_J;
 
-// Work item of the persistent batched sweep: one tile of one request's
-// forward sweep (kind 0: 256 lanes = band entries x0.., triangle chunk c) or
+// Work item of the persistent batched sweeps: one tile of one request's
+// forward sweep (kind 0: FWD_CHUNK band entries from x0, triangle chunk c) or
 // gradient sweep (kind 1: entry chunk c of epc entries, triangles x0.. x0+vtpb).
 struct SweepItem {
   int kind, req, x0, c;
@@ -86,12 +93,17 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_band_fill(const GridC& g, const double* sigma6, double qmax, const int32_t* cnt,
                             const int32_t* off, int64_t n_slots, BandDev b, hipStream_t s);
 
-hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces, int nt,
+hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces,
+                            const int32_t* flags, int nt,
                             float* tri_rec, MeshInfo* info, double* block_tmp, int tmp_blocks, hipStream_t s);
 int mesh_prep_blocks(int nt);
 
-hipError_t launch_fwd_sweep(int mode, const float4* kf, int64_t nE, const float* tri_rec, int nt,
-                            int tris_per_chunk, int n_chunks, float2* part, hipStream_t s);
+// Forward sweep with band entries on lanes: ceil(nE / FWD_CHUNK) x n_chunks
+// blocks, triangle chunks of tris_per_chunk strip-ordered triangles; writes
+// part[chunk][nE].
+hipError_t launch_fwd_lanes(int mode, const float4* kf, int64_t nE, const float* tri_rec, int nt, int tris_per_chunk,
+                            int n_chunks, float2* part, hipStream_t s);
+
 hipError_t launch_fwd_finalize(int mode, const GridC& g, BandDev b, const float2* part, int n_chunks,
                                const MeshInfo* info, float2* spec_out, float2* xhalf, hipStream_t s);
 hipError_t launch_spec_scatter(const GridC& g, BandDev b, const float2* spec, float2* xhalf, hipStream_t s);
@@ -115,7 +127,8 @@ hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, 
                              hipStream_t s);
 hipError_t launch_surface_scalar(const float* red, const float* tri_rec, int nt, const MeshInfo* info,
                                  double* out_R, hipStream_t s);
-hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, int nt,
+hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, const int32_t* flags,
+                                int nt,
                                 const int32_t* csr_off, const int32_t* csr_ent, const float* red,
                                 const double* R, float* dV, hipStream_t s);
 

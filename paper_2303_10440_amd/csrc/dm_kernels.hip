@@ -67,14 +67,22 @@ __device__ __forceinline__ float sinc_from(float x, float sinx, float inv_x) {
   return pick(x < 0.5f, p, sinx * inv_x);
 }
 
-// Integer-frequency phase of vertex 1 plus the two relative phases (revolutions).
-__device__ __forceinline__ void tri_phases(float kx, float ky, float kz, const float* r, float& t1, float& d2,
-                                           float& d3) {
+// Integer-frequency phase of the record's vertex 3 (revolutions, integer
+// part removed exactly) and the phases of vertices 2 and 3 relative to 1.
+__device__ __forceinline__ float vertex3_phase(float kx, float ky, float kz, const float* r) {
   float th = fmaf(kz, r[2], fmaf(ky, r[1], kx * r[0]));   // exact: 12-bit grid part
   th -= __builtin_rintf(th);
-  t1 = th + fmaf(kz, r[5], fmaf(ky, r[4], kx * r[3]));
+  return th + fmaf(kz, r[5], fmaf(ky, r[4], kx * r[3]));
+}
+__device__ __forceinline__ void rel_phases(float kx, float ky, float kz, const float* r, float& d2, float& d3) {
   d2 = fmaf(kz, r[8], fmaf(ky, r[7], kx * r[6]));
   d3 = fmaf(kz, r[11], fmaf(ky, r[10], kx * r[9]));
+}
+// Phase of vertex 1 and the two relative phases.
+__device__ __forceinline__ void tri_phases(float kx, float ky, float kz, const float* r, float& t1, float& d2,
+                                           float& d3) {
+  rel_phases(kx, ky, kz, r, d2, d3);
+  t1 = vertex3_phase(kx, ky, kz, r) - d3;
 }
 
 // Wrap revolutions into [0, 1) for the hardware sine/cosine (v_fract_f32).
@@ -482,7 +490,8 @@ __global__ void __launch_bounds__(PREP_T) k_prep_centroid(GridC g, const float* 
 
 template <int MODE>
 __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __restrict__ V,
-                                                        const int32_t* __restrict__ F, int nt,
+                                                        const int32_t* __restrict__ F,
+                                                        const int32_t* __restrict__ flags, int nt,
                                                         const MeshInfo* __restrict__ info,
                                                         float* __restrict__ rec, double* __restrict__ tmp) {
   __shared__ double sh[PREP_T];
@@ -496,8 +505,10 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
     }
     float* r = rec + (size_t)t * TRI_REC;
     double e2[3], e3[3], a[3], b[3];
+    const int fl = flags[t];
+    const double sgn = (fl & TRI_REVERSED) ? -1.0 : 1.0;
     for (int j = 0; j < 3; ++j) {
-      const double u = (v[0][j] - c[j]) / g.L[j];
+      const double u = (v[2][j] - c[j]) / g.L[j];
       const double uh = rint(u * (double)PHASE_GRID) / (double)PHASE_GRID;
       r[j] = (float)uh;
       r[3 + j] = (float)(u - uh);
@@ -508,7 +519,8 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
       a[j] = v[1][j] - c[j];
       b[j] = v[2][j] - c[j];
     }
-    const double n[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2], e2[0] * e3[1] - e2[1] * e3[0]};
+    const double n[3] = {sgn * (e2[1] * e3[2] - e2[2] * e3[1]), sgn * (e2[2] * e3[0] - e2[0] * e3[2]),
+                         sgn * (e2[0] * e3[1] - e2[1] * e3[0])};
     const double twoA = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     if (MODE == 0) {
       for (int j = 0; j < 3; ++j) r[12 + j] = (float)(n[j] / g.L[j]);
@@ -517,11 +529,11 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
       r[13] = 0.0f;
       r[14] = 0.0f;
     }
-    r[15] = 0.0f;
+    r[15] = (fl & TRI_STRIP_START) ? 1.0f : 0.0f;
     area += 0.5 * twoA;
     const double a0[3] = {v[0][0] - c[0], v[0][1] - c[1], v[0][2] - c[2]};
-    vol += (a0[0] * (a[1] * b[2] - a[2] * b[1]) + a0[1] * (a[2] * b[0] - a[0] * b[2]) +
-            a0[2] * (a[0] * b[1] - a[1] * b[0])) / 6.0;
+    vol += sgn * (a0[0] * (a[1] * b[2] - a[2] * b[1]) + a0[1] * (a[2] * b[0] - a[0] * b[2]) +
+                  a0[2] * (a[0] * b[1] - a[1] * b[0])) / 6.0;
   }
   area = block_sum(area, sh);
   vol = block_sum(vol, sh);
@@ -550,35 +562,161 @@ __global__ void __launch_bounds__(PREP_T) k_prep_totals(const double* __restrict
 // ------------------------------------------------------------ forward sweep
 constexpr int SWEEP_T = 256;
 
-// Forward sweep over one tile: lane = band entry e, triangles [t0, t1).
+// Forward sweep with band entries on lanes (FWD_J entries per lane; a block
+// covers FWD_CHUNK entries) over a range of
+// strip-ordered triangles.  Each triangle adds one vertex: its phase factor
+// is computed, the other two are carried over from the previous triangle of
+// the strip.  Pairs are evaluated in closed (Lagrange) form,
+//   f = (-(b-a) E1 + b E2 - a E3) / (4 pi^2 a b (b-a)),
+// E_p = e^{-2 pi i t_p}, a and b the phases of vertices 2 and 3 relative to
+// vertex 1 (all in revolutions).  Pairs with a node gap below FWD_LAG_GAP or a
+// spread below one radian are queued in LDS and evaluated by dd3_acc on full
+// waves after every second triangle; their sums collect in LDS rows per
+// entry and are added to the register sums at the end.
+constexpr float FWD_LAG_GAP = 0.01f;
+constexpr float INV_4PI2_F = 0.025330295910584444f;   // 1 / (4 pi^2)
+
+// Queued pairs of two consecutive triangles share one pass; each triangle of
+// the pair (parity p) has its own LDS row, so no two queued pairs of a pass
+// add to the same slot.
+struct FwdLds {
+  uint16_t queue[4][2 * 64 * FWD_J];
+  float2 fb[4][2][FWD_J][64];
+};
+
+// One triangle: X holds the phase factors of vertex 1, Y of vertex 2 (both
+// computed here at a strip start); on return X holds those of vertex 3, so
+// the next triangle of the strip is processed with the roles of X and Y
+// swapped.  Pairs that need the stable scheme are appended to the queue.
 template <int MODE>
-__device__ __forceinline__ void fwd_tile(const float4* __restrict__ kf, int nE, const float* __restrict__ rec, int t0,
-                                         int t1, int e, float2* __restrict__ part_row) {
-  float kx = 0.0f, ky = 0.0f, kz = 0.0f;
-  if (e < nE) {
-    const float4 q = kf[e];
-    kx = q.x;
-    ky = q.y;
-    kz = q.z;
+__device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int parity, const float (&kx)[FWD_J],
+                                              const float (&ky)[FWD_J], const float (&kz)[FWD_J], uint32_t vm,
+                                              float (&Xr)[FWD_J], float (&Xi)[FWD_J], float (&Yr)[FWD_J],
+                                              float (&Yi)[FWD_J], float (&ar)[FWD_J], float (&ai)[FWD_J], int lane,
+                                              uint16_t* queue, int& nq) {
+  if (start) {
+#pragma unroll
+    for (int j = 0; j < FWD_J; ++j) {
+      float d2, d3;
+      rel_phases(kx[j], ky[j], kz[j], r, d2, d3);
+      const float t1 = vertex3_phase(kx[j], ky[j], kz[j], r) - d3;
+      const float q1 = wrap(t1), q2 = wrap(t1 + d2);
+      Xr[j] = __builtin_amdgcn_cosf(q1);
+      Xi[j] = -__builtin_amdgcn_sinf(q1);
+      Yr[j] = __builtin_amdgcn_cosf(q2);
+      Yi[j] = -__builtin_amdgcn_sinf(q2);
+    }
   }
-  float ar = 0.0f, ai = 0.0f;
-  for (int t = t0; t < t1; ++t) {
-    const float* r = rec + (size_t)t * TRI_REC;
-    float tv, d2, d3;
-    tri_phases(kx, ky, kz, r, tv, d2, d3);
-    const float w = MODE == 0 ? fmaf(kz, r[14], fmaf(ky, r[13], kx * r[12])) : r[12];
-    dd3_acc(tv, d2, d3, w, ar, ai);
+#pragma unroll
+  for (int j = 0; j < FWD_J; ++j) {
+    float a, b;
+    rel_phases(kx[j], ky[j], kz[j], r, a, b);
+    const float q3 = wrap(vertex3_phase(kx[j], ky[j], kz[j], r));
+    const float Nr = __builtin_amdgcn_cosf(q3), Ni = -__builtin_amdgcn_sinf(q3);
+    const float c = b - a;
+    const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
+    const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
+    const bool fast = mn >= FWD_LAG_GAP && mx >= SERIES_REV;
+    const float wt = MODE == 0 ? fmaf(kz[j], r[14], fmaf(ky[j], r[13], kx[j] * r[12])) : r[12];
+    const float kap = wt * __builtin_amdgcn_rcpf(fast ? a * b * c : 1.0f) * INV_4PI2_F;
+    const float kk = fast ? kap : 0.0f;
+    const float tr = fmaf(-c, Xr[j], fmaf(b, Yr[j], -a * Nr));
+    const float ti = fmaf(-c, Xi[j], fmaf(b, Yi[j], -a * Ni));
+    ar[j] = fmaf(kk, tr, ar[j]);
+    ai[j] = fmaf(kk, ti, ai[j]);
+    const bool need = !fast && ((vm >> j) & 1u);
+    const uint64_t bal = __ballot(need);
+    if (need) {
+      const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      queue[pos] = (uint16_t)((parity << 8) | (j << 6) | lane);
+    }
+    nq += __popcll(bal);
+    Xr[j] = Nr;
+    Xi[j] = Ni;
   }
-  if (e < nE) part_row[e] = make_float2(ar, ai);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stable scheme for the queued pairs of triangles r0 (parity 0) and r1 (parity 1).
+template <int MODE>
+__device__ __forceinline__ void fwd_lanes_flush(const float* r0, const float* r1, const float4* __restrict__ kf,
+                                                int64_t ew, int lane, int w, int nq, FwdLds& L) {
+  wave_lds_sync();
+  for (int q0 = 0; q0 < nq; q0 += 64) {
+    if (q0 + lane < nq) {
+      const int it = L.queue[w][q0 + lane];
+      const int p = it >> 8, jj = (it >> 6) & 3, ll = it & 63;
+      const float* r = p ? r1 : r0;
+      const float4 k = kf[ew + 64 * jj + ll];
+      float t1, d2, d3;
+      tri_phases(k.x, k.y, k.z, r, t1, d2, d3);
+      const float wt = MODE == 0 ? fmaf(k.z, r[14], fmaf(k.y, r[13], k.x * r[12])) : r[12];
+      float fr = 0.0f, fi = 0.0f;
+      dd3_acc(t1, d2, d3, wt, fr, fi);
+      float2& slot = L.fb[w][p][jj][ll];
+      slot = make_float2(slot.x + fr, slot.y + fi);
+    }
+  }
+  wave_lds_sync();
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_fwd_sweep(const float4* __restrict__ kf, int nE,
+__device__ __forceinline__ void fwd_lanes_tile(const float4* __restrict__ kf, int64_t nE, const float* __restrict__ rec,
+                                               int t0, int t1, int64_t e_chunk, float2* __restrict__ part_row,
+                                               FwdLds& L) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t ew = e_chunk + (int64_t)w * 64 * FWD_J;
+  float kx[FWD_J], ky[FWD_J], kz[FWD_J], ar[FWD_J], ai[FWD_J];
+  float Xr[FWD_J], Xi[FWD_J], Yr[FWD_J], Yi[FWD_J];
+  uint32_t vm = 0;
+#pragma unroll
+  for (int j = 0; j < FWD_J; ++j) {
+    const int64_t e = ew + 64 * j + lane;
+    kx[j] = ky[j] = kz[j] = ar[j] = ai[j] = 0.0f;
+    Xr[j] = Xi[j] = Yr[j] = Yi[j] = 0.0f;
+    if (e < nE) {
+      const float4 k = kf[e];
+      kx[j] = k.x;
+      ky[j] = k.y;
+      kz[j] = k.z;
+      vm |= 1u << j;
+    }
+    L.fb[w][0][j][lane] = make_float2(0.0f, 0.0f);
+    L.fb[w][1][j][lane] = make_float2(0.0f, 0.0f);
+  }
+  for (int t = t0; t < t1; t += 2) {
+    const float* r = rec + (size_t)t * TRI_REC;
+    int nq = 0;
+    fwd_lanes_tri<MODE>(r, t == t0 || r[15] != 0.0f, 0, kx, ky, kz, vm, Xr, Xi, Yr, Yi, ar, ai, lane, L.queue[w], nq);
+    const float* r2 = r + TRI_REC;
+    if (t + 1 < t1)
+      fwd_lanes_tri<MODE>(r2, r2[15] != 0.0f, 1, kx, ky, kz, vm, Yr, Yi, Xr, Xi, ar, ai, lane, L.queue[w], nq);
+    fwd_lanes_flush<MODE>(r, r2, kf, ew, lane, w, nq, L);
+  }
+#pragma unroll
+  for (int j = 0; j < FWD_J; ++j) {
+    const int64_t e = ew + 64 * j + lane;
+    if (e < nE) {
+      const float2 f0 = L.fb[w][0][j][lane], f1 = L.fb[w][1][j][lane];
+      part_row[e] = make_float2(ar[j] + (f0.x + f1.x), ai[j] + (f0.y + f1.y));
+    }
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(SWEEP_T) k_fwd_lanes(const float4* __restrict__ kf, int64_t nE,
                                                          const float* __restrict__ rec, int nt, int tpc,
                                                          float2* __restrict__ part) {
+  __shared__ FwdLds L;
   const int t0 = blockIdx.y * tpc;
-  fwd_tile<MODE>(kf, nE, rec, t0, min(nt, t0 + tpc), blockIdx.x * SWEEP_T + threadIdx.x,
-                 part + (size_t)blockIdx.y * nE);
+  fwd_lanes_tile<MODE>(kf, nE, rec, t0, min(nt, t0 + tpc), (int64_t)blockIdx.x * FWD_CHUNK,
+                       part + (size_t)blockIdx.y * nE, L);
 }
 
 // Phase factor e^{-i xi.(c - origin)} for integer frequency k (float32 after
@@ -895,18 +1033,18 @@ __device__ __forceinline__ int next_item(int* counter, int* slot) {
 __global__ void __launch_bounds__(SWEEP_T) k_batch_fwd(const SweepItem* __restrict__ items, int n_items,
                                                          const SweepReq* __restrict__ reqs, int* __restrict__ counter) {
   __shared__ int slot;
+  __shared__ FwdLds L;
   for (;;) {
     const int it = next_item(counter, &slot);
     if (it >= n_items) return;
     const SweepItem w = items[it];
     const SweepReq q = reqs[w.req];
-    const int lane = w.x0 + (int)threadIdx.x;
     const int t0 = w.c * q.tpc, t1 = min(q.nt, t0 + q.tpc);
     float2* row = q.fpart + (size_t)w.c * q.nE;
     if (q.mode == 0)
-      fwd_tile<0>(q.kf, q.nE, q.rec, t0, t1, lane, row);
+      fwd_lanes_tile<0>(q.kf, q.nE, q.rec, t0, t1, w.x0, row, L);
     else
-      fwd_tile<1>(q.kf, q.nE, q.rec, t0, t1, lane, row);
+      fwd_lanes_tile<1>(q.kf, q.nE, q.rec, t0, t1, w.x0, row, L);
   }
 }
 
@@ -964,7 +1102,8 @@ __global__ void __launch_bounds__(PREP_T) k_surface_scalar(const float* __restri
 }
 
 template <int MODE>
-__global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32_t* __restrict__ F, int nt,
+__global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32_t* __restrict__ F,
+                                const int32_t* __restrict__ flags, int nt,
                                 const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
                                 const float* __restrict__ red, const double* __restrict__ Rp,
                                 float* __restrict__ dV) {
@@ -984,7 +1123,7 @@ __global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32
     const float b[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
     const float n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
     if (MODE == 0) {
-      const float Q = red[(size_t)p * nt + t];
+      const float Q = (flags[t] & TRI_REVERSED) ? -red[(size_t)p * nt + t] : red[(size_t)p * nt + t];
       for (int j = 0; j < 3; ++j) g[j] = fmaf(n[j], Q, g[j]);
     } else {
       const float twoA = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
@@ -1072,28 +1211,31 @@ int mesh_prep_blocks(int nt) {
   return b < 1 ? 1 : (b > 1024 ? 1024 : b);
 }
 
-hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces, int nt,
+hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces,
+                            const int32_t* flags, int nt,
                             float* tri_rec, MeshInfo* info, double* block_tmp, int tmp_blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_prep_centroid, dim3(1), dim3(PREP_T), 0, s, g, verts, nv, info);
   if (mode == 0)
-    hipLaunchKernelGGL(k_prep_tris<0>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, nt,
+    hipLaunchKernelGGL(k_prep_tris<0>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, flags, nt,
                        (const MeshInfo*)info, tri_rec, block_tmp);
   else
-    hipLaunchKernelGGL(k_prep_tris<1>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, nt,
+    hipLaunchKernelGGL(k_prep_tris<1>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, flags, nt,
                        (const MeshInfo*)info, tri_rec, block_tmp);
   hipLaunchKernelGGL(k_prep_totals, dim3(1), dim3(PREP_T), 0, s, (const double*)block_tmp, tmp_blocks, info);
   return hipGetLastError();
 }
 
-hipError_t launch_fwd_sweep(int mode, const float4* kf, int64_t nE, const float* tri_rec, int nt,
-                            int tris_per_chunk, int n_chunks, float2* part, hipStream_t s) {
-  const dim3 grid(blocks_for(nE, SWEEP_T), (unsigned)n_chunks);
+hipError_t launch_fwd_lanes(int mode, const float4* kf, int64_t nE, const float* tri_rec, int nt, int tris_per_chunk,
+                            int n_chunks, float2* part, hipStream_t s) {
+  if (tris_per_chunk < 1 || (int64_t)tris_per_chunk * n_chunks < nt) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((nE + FWD_CHUNK - 1) / FWD_CHUNK), (unsigned)n_chunks);
   if (mode == 0)
-    hipLaunchKernelGGL(k_fwd_sweep<0>, grid, dim3(SWEEP_T), 0, s, kf, (int)nE, tri_rec, nt, tris_per_chunk, part);
+    hipLaunchKernelGGL(k_fwd_lanes<0>, grid, dim3(SWEEP_T), 0, s, kf, nE, tri_rec, nt, tris_per_chunk, part);
   else
-    hipLaunchKernelGGL(k_fwd_sweep<1>, grid, dim3(SWEEP_T), 0, s, kf, (int)nE, tri_rec, nt, tris_per_chunk, part);
+    hipLaunchKernelGGL(k_fwd_lanes<1>, grid, dim3(SWEEP_T), 0, s, kf, nE, tri_rec, nt, tris_per_chunk, part);
   return hipGetLastError();
 }
+
 
 hipError_t launch_fwd_finalize(int mode, const GridC& g, BandDev b, const float2* part, int n_chunks,
                                const MeshInfo* info, float2* spec_out, float2* xhalf, hipStream_t s) {
@@ -1186,14 +1328,17 @@ hipError_t launch_surface_scalar(const float* red, const float* tri_rec, int nt,
   return hipGetLastError();
 }
 
-hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, int nt,
+hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, const int32_t* flags,
+                                int nt,
                                 const int32_t* csr_off, const int32_t* csr_ent, const float* red,
                                 const double* R, float* dV, hipStream_t s) {
   const dim3 grid(blocks_for(nv, 128));
   if (mode == 0)
-    hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(128), 0, s, verts, nv, faces, nt, csr_off, csr_ent, red, R, dV);
+    hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(128), 0, s, verts, nv, faces, flags, nt, csr_off, csr_ent, red, R,
+                       dV);
   else
-    hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(128), 0, s, verts, nv, faces, nt, csr_off, csr_ent, red, R, dV);
+    hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(128), 0, s, verts, nv, faces, flags, nt, csr_off, csr_ent, red, R,
+                       dV);
   return hipGetLastError();
 }
 
