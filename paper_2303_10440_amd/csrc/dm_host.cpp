@@ -464,13 +464,18 @@ struct SweepPlan {
   int sub = 1, tpb = 1;   // lane-per-entry gradient sweep: entry chunks per block, triangles per block
 };
 
+// Both sweeps hold about 1280 blocks of 4 waves resident at once (5 waves
+// per SIMD); a grid of several times that keeps the last, partly filled round
+// short.
+constexpr int64_t FWD_TARGET_BLOCKS = 10240, VJP_TARGET_BLOCKS = 10240;
+
 // Forward sweep (band entries on lanes): blocks of FWD_CHUNK entries times
-// triangle chunks, about 2560 blocks in all, chunks of at least 64 triangles.
+// triangle chunks of at least 32 triangles, FWD_TARGET_BLOCKS blocks in all.
 SweepPlan plan_fwd(int64_t nE, int nt) {
   SweepPlan sp;
   const int64_t eblocks = std::max<int64_t>(1, (nE + FWD_CHUNK - 1) / FWD_CHUNK);
-  const int64_t want = (2560 + eblocks - 1) / eblocks;
-  const int64_t most = std::max<int64_t>(1, nt / 64);
+  const int64_t want = (FWD_TARGET_BLOCKS + eblocks - 1) / eblocks;
+  const int64_t most = std::max<int64_t>(1, nt / 32);
   sp.n_chunks = (int)std::max<int64_t>(1, std::min(want, most));
   sp.per_chunk = std::max(1, (nt + sp.n_chunks - 1) / sp.n_chunks);
   sp.n_chunks = std::max(1, (nt + sp.per_chunk - 1) / sp.per_chunk);
@@ -480,15 +485,15 @@ SweepPlan plan_fwd(int64_t nE, int nt) {
 // Gradient sweep (lane per band entry): n_chunks blocks along the band of
 // sub x VJP_CHUNK entries each, at most 64 of them so the partials stay
 // bounded (4 B x channels x triangles x 64), times triangle chunks of tpb so
-// the grid has about 4096 blocks.
+// the grid has about VJP_TARGET_BLOCKS blocks.
 SweepPlan plan_vjp(int64_t nE, int nt) {
   SweepPlan sp;
   const int64_t units = std::max<int64_t>(1, (nE + VJP_CHUNK - 1) / VJP_CHUNK);
   sp.sub = (int)((units + 63) / 64);
   sp.n_chunks = (int)((units + sp.sub - 1) / sp.sub);
   sp.per_chunk = sp.sub * VJP_CHUNK;
-  const int64_t want = (4096 + sp.n_chunks - 1) / sp.n_chunks;
-  const int64_t most = std::max<int64_t>(1, (nt + 31) / 32);
+  const int64_t want = (VJP_TARGET_BLOCKS + sp.n_chunks - 1) / sp.n_chunks;
+  const int64_t most = std::max<int64_t>(1, (nt + 15) / 16);
   const int64_t tchunks = std::max<int64_t>((nt + VJP_TPB_MAX - 1) / VJP_TPB_MAX, std::min(want, most));
   sp.tpb = (int)std::max<int64_t>(1, (nt + tchunks - 1) / tchunks);
   return sp;

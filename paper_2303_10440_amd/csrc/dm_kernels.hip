@@ -571,25 +571,28 @@ constexpr int SWEEP_T = 256;
 // E_p = e^{-2 pi i t_p}, a and b the phases of vertices 2 and 3 relative to
 // vertex 1 (all in revolutions).  Pairs with a node gap below FWD_LAG_GAP or a
 // spread below one radian are queued in LDS and evaluated by dd3_acc on full
-// waves after every second triangle; their sums collect in LDS rows per
+// waves after every FWD_TQ triangles; their sums collect in an LDS row per
 // entry and are added to the register sums at the end.
-constexpr float FWD_LAG_GAP = 0.01f;
+constexpr float FWD_LAG_GAP = 0.005f;
 constexpr float INV_4PI2_F = 0.025330295910584444f;   // 1 / (4 pi^2)
+constexpr int FWD_TQ = 4;   // triangles whose queued pairs share one pass
 
-// Queued pairs of two consecutive triangles share one pass; each triangle of
-// the pair (parity p) has its own LDS row, so no two queued pairs of a pass
-// add to the same slot.
+// Queued pairs of FWD_TQ consecutive triangles share one pass.  Within a pass
+// the sums are added to the per-entry LDS row triangle by triangle (a
+// triangle queues each entry at most once), so no two lanes add to the same
+// slot at once and the order of the additions is fixed.
 struct FwdLds {
-  uint16_t queue[4][2 * 64 * FWD_J];
-  float2 fb[4][2][FWD_J][64];
+  uint16_t queue[4][FWD_TQ * 64 * FWD_J];
+  float2 fb[4][FWD_J][64];
 };
 
 // One triangle: X holds the phase factors of vertex 1, Y of vertex 2 (both
 // computed here at a strip start); on return X holds those of vertex 3, so
 // the next triangle of the strip is processed with the roles of X and Y
-// swapped.  Pairs that need the stable scheme are appended to the queue.
+// swapped.  Pairs that need the stable scheme are appended to the queue with
+// the triangle's tag (its offset in the group sharing a pass).
 template <int MODE>
-__device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int parity, const float (&kx)[FWD_J],
+__device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int tag, const float (&kx)[FWD_J],
                                               const float (&ky)[FWD_J], const float (&kz)[FWD_J], uint32_t vm,
                                               float (&Xr)[FWD_J], float (&Xi)[FWD_J], float (&Yr)[FWD_J],
                                               float (&Yi)[FWD_J], float (&ar)[FWD_J], float (&ai)[FWD_J], int lane,
@@ -629,7 +632,7 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int pa
     if (need) {
       const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      queue[pos] = (uint16_t)((parity << 8) | (j << 6) | lane);
+      queue[pos] = (uint16_t)((tag << 8) | (j << 6) | lane);
     }
     nq += __popcll(bal);
     Xr[j] = Nr;
@@ -643,27 +646,37 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stable scheme for the queued pairs of triangles r0 (parity 0) and r1 (parity 1).
+// Stable scheme for the queued pairs of the triangles starting at r (tag p =
+// triangle r + p TRI_REC).
 template <int MODE>
-__device__ __forceinline__ void fwd_lanes_flush(const float* r0, const float* r1, const float4* __restrict__ kf,
-                                                int64_t ew, int lane, int w, int nq, FwdLds& L) {
+__device__ __forceinline__ void fwd_lanes_flush(const float* r, const float4* __restrict__ kf, int64_t ew, int lane,
+                                                int w, int nq, FwdLds& L) {
   wave_lds_sync();
   for (int q0 = 0; q0 < nq; q0 += 64) {
-    if (q0 + lane < nq) {
+    const bool act = q0 + lane < nq;
+    int p = -1, jj = 0, ll = 0;
+    float fr = 0.0f, fi = 0.0f;
+    if (act) {
       const int it = L.queue[w][q0 + lane];
-      const int p = it >> 8, jj = (it >> 6) & 3, ll = it & 63;
-      const float* r = p ? r1 : r0;
+      p = it >> 8;
+      jj = (it >> 6) & 3;
+      ll = it & 63;
+      const float* rp = r + (size_t)p * TRI_REC;
       const float4 k = kf[ew + 64 * jj + ll];
       float t1, d2, d3;
-      tri_phases(k.x, k.y, k.z, r, t1, d2, d3);
-      const float wt = MODE == 0 ? fmaf(k.z, r[14], fmaf(k.y, r[13], k.x * r[12])) : r[12];
-      float fr = 0.0f, fi = 0.0f;
+      tri_phases(k.x, k.y, k.z, rp, t1, d2, d3);
+      const float wt = MODE == 0 ? fmaf(k.z, rp[14], fmaf(k.y, rp[13], k.x * rp[12])) : rp[12];
       dd3_acc(t1, d2, d3, wt, fr, fi);
-      float2& slot = L.fb[w][p][jj][ll];
-      slot = make_float2(slot.x + fr, slot.y + fi);
+    }
+#pragma unroll
+    for (int q = 0; q < FWD_TQ; ++q) {
+      if (p == q) {
+        float2& slot = L.fb[w][jj][ll];
+        slot = make_float2(slot.x + fr, slot.y + fi);
+      }
+      wave_lds_sync();
     }
   }
-  wave_lds_sync();
 }
 
 template <int MODE>
@@ -687,24 +700,30 @@ __device__ __forceinline__ void fwd_lanes_tile(const float4* __restrict__ kf, in
       kz[j] = k.z;
       vm |= 1u << j;
     }
-    L.fb[w][0][j][lane] = make_float2(0.0f, 0.0f);
-    L.fb[w][1][j][lane] = make_float2(0.0f, 0.0f);
+    L.fb[w][j][lane] = make_float2(0.0f, 0.0f);
   }
-  for (int t = t0; t < t1; t += 2) {
+  for (int t = t0; t < t1; t += FWD_TQ) {
     const float* r = rec + (size_t)t * TRI_REC;
     int nq = 0;
+    // triangles t, t+1, ... alternate the roles of X and Y (see fwd_lanes_tri)
     fwd_lanes_tri<MODE>(r, t == t0 || r[15] != 0.0f, 0, kx, ky, kz, vm, Xr, Xi, Yr, Yi, ar, ai, lane, L.queue[w], nq);
-    const float* r2 = r + TRI_REC;
     if (t + 1 < t1)
-      fwd_lanes_tri<MODE>(r2, r2[15] != 0.0f, 1, kx, ky, kz, vm, Yr, Yi, Xr, Xi, ar, ai, lane, L.queue[w], nq);
-    fwd_lanes_flush<MODE>(r, r2, kf, ew, lane, w, nq, L);
+      fwd_lanes_tri<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, 1, kx, ky, kz, vm, Yr, Yi, Xr, Xi, ar, ai, lane,
+                          L.queue[w], nq);
+    if (t + 2 < t1)
+      fwd_lanes_tri<MODE>(r + 2 * TRI_REC, r[2 * TRI_REC + 15] != 0.0f, 2, kx, ky, kz, vm, Xr, Xi, Yr, Yi, ar, ai,
+                          lane, L.queue[w], nq);
+    if (t + 3 < t1)
+      fwd_lanes_tri<MODE>(r + 3 * TRI_REC, r[3 * TRI_REC + 15] != 0.0f, 3, kx, ky, kz, vm, Yr, Yi, Xr, Xi, ar, ai,
+                          lane, L.queue[w], nq);
+    fwd_lanes_flush<MODE>(r, kf, ew, lane, w, nq, L);
   }
 #pragma unroll
   for (int j = 0; j < FWD_J; ++j) {
     const int64_t e = ew + 64 * j + lane;
     if (e < nE) {
-      const float2 f0 = L.fb[w][0][j][lane], f1 = L.fb[w][1][j][lane];
-      part_row[e] = make_float2(ar[j] + (f0.x + f1.x), ai[j] + (f0.y + f1.y));
+      const float2 f = L.fb[w][j][lane];
+      part_row[e] = make_float2(ar[j] + f.x, ai[j] + f.y);
     }
   }
 }
@@ -872,13 +891,29 @@ __global__ void __launch_bounds__(64) k_dsig_final(const double* __restrict__ pa
 }
 
 // --------------------------------------------------------------- VJP sweep
+// Sum over the 64 lanes of a wave in a fixed order (quads, half rows, rows,
+// then row pairs, with DPP lane moves); the total ends in lane 63.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_src(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_src<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_src<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_src<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_src<0x140, 0xF>(v);   // row_mirror
+  v += dpp_src<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_src<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Lane-per-entry gradient sweep.  A block owns n_sub consecutive entry chunks
 // of VJP_CHUNK band entries (in chunk g: wave w, step j, lane l -> entry
 // 64 (w VJP_J + j) + l) and a range of at most VJP_TPB_MAX triangles, which are
 // wave-uniform.  Pairs whose nodes are too close for the closed form are
 // queued in LDS and evaluated by vjp_pair after each triangle, so the stable
 // branch runs on full waves instead of diverging.  Per triangle the lane sums
-// are reduced over the wave (butterfly, lane 0's order), over the 4 waves and
+// are reduced over the wave (wave_sum), over the 4 waves and
 // then over the entry chunks, each in a fixed order, into part_out[NC][nt].
 constexpr int VJP_TB = 32;   // triangles between block-level merges
 
@@ -981,9 +1016,7 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
         }
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) {
-          float v = acc[ch];
-#pragma unroll
-          for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+          const float v = wave_sum(acc[ch]);
           if (lane == 0) L.tot[w][tt][ch] = v;
         }
       }
