@@ -467,7 +467,7 @@ struct SweepPlan {
 // Both sweeps hold about 1280 blocks of 4 waves resident at once (5 waves
 // per SIMD); a grid of several times that keeps the last, partly filled round
 // short.
-constexpr int64_t FWD_TARGET_BLOCKS = 10240, VJP_TARGET_BLOCKS = 10240;
+constexpr int64_t FWD_TARGET_BLOCKS = 20480, VJP_TARGET_BLOCKS = 20480;
 
 // Forward sweep (band entries on lanes): blocks of FWD_CHUNK entries times
 // triangle chunks of at least 32 triangles, FWD_TARGET_BLOCKS blocks in all.
@@ -483,17 +483,18 @@ SweepPlan plan_fwd(int64_t nE, int nt) {
 }
 
 // Gradient sweep (lane per band entry): n_chunks blocks along the band of
-// sub x VJP_CHUNK entries each, at most 64 of them so the partials stay
+// sub x vjp_chunk(mode) entries each, at most 64 of them so the partials stay
 // bounded (4 B x channels x triangles x 64), times triangle chunks of tpb so
 // the grid has about VJP_TARGET_BLOCKS blocks.
-SweepPlan plan_vjp(int64_t nE, int nt) {
+SweepPlan plan_vjp(int64_t nE, int nt, int mode) {
   SweepPlan sp;
-  const int64_t units = std::max<int64_t>(1, (nE + VJP_CHUNK - 1) / VJP_CHUNK);
+  const int64_t chunk = vjp_chunk(mode);
+  const int64_t units = std::max<int64_t>(1, (nE + chunk - 1) / chunk);
   sp.sub = (int)((units + 63) / 64);
   sp.n_chunks = (int)((units + sp.sub - 1) / sp.sub);
-  sp.per_chunk = sp.sub * VJP_CHUNK;
+  sp.per_chunk = (int)(sp.sub * chunk);
   const int64_t want = (VJP_TARGET_BLOCKS + sp.n_chunks - 1) / sp.n_chunks;
-  const int64_t most = std::max<int64_t>(1, (nt + 15) / 16);
+  const int64_t most = std::max<int64_t>(1, (nt + 7) / 8);
   const int64_t tchunks = std::max<int64_t>((nt + VJP_TPB_MAX - 1) / VJP_TPB_MAX, std::min(want, most));
   sp.tpb = (int)std::max<int64_t>(1, (nt + tchunks - 1) / tchunks);
   return sp;
@@ -581,7 +582,7 @@ struct ReqPlan {
 // same whichever other requests share its batch.
 // At least 640 triangles per forward tile so small requests still give long
 // sweeps, at most 8 forward chunks so the partials of large requests stay
-// bounded (8 B x entries x 8).  Gradient items cover sub x VJP_CHUNK entries
+// bounded (8 B x entries x 8).  Gradient items cover sub x vjp_chunk(mode) entries
 // (at most 64 chunks, as in plan_vjp) and up to VJP_TPB_MAX triangles.
 SweepPlan plan_fwd_batch(int64_t nE, int nt) {
   SweepPlan sp;
@@ -591,8 +592,8 @@ SweepPlan plan_fwd_batch(int64_t nE, int nt) {
   return sp;
 }
 
-SweepPlan plan_vjp_batch(int64_t nE, int nt) {
-  SweepPlan sp = plan_vjp(nE, nt);
+SweepPlan plan_vjp_batch(int64_t nE, int nt, int mode) {
+  SweepPlan sp = plan_vjp(nE, nt, mode);
   int tpb = 32;   // about 2^20 pairs per gradient item
   while (tpb < VJP_TPB_MAX && (int64_t)2 * tpb * sp.per_chunk <= ((int64_t)1 << 20)) tpb *= 2;
   sp.tpb = std::max(1, std::min(nt, tpb));
@@ -613,7 +614,7 @@ dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch) {
   P.empty = P.nE == 0 || P.nt == 0;
   P.need_spec = (P.image && !P.spec_in) || (P.dS && !P.spec_in) || P.spec_out;
   P.fsp = batch ? plan_fwd_batch(P.nE, P.nt) : plan_fwd(P.nE, P.nt);
-  P.vsp = batch ? plan_vjp_batch(P.nE, P.nt) : plan_vjp(P.nE, P.nt);
+  P.vsp = batch ? plan_vjp_batch(P.nE, P.nt, P.g.mode) : plan_vjp(P.nE, P.nt, P.g.mode);
   P.nc = nchannels(P.mode);
   P.prep_blocks = mesh_prep_blocks(P.nt);
   P.adj_blocks = adjoint_blocks(P.gc);
@@ -800,9 +801,9 @@ void fill_plan(ReqPlan& P, const dm_request& r) {
 // per-request sweep descriptors and the queue counter.
 struct BatchLayout {
   std::vector<size_t> off;
-  std::vector<SweepItem> items;   // forward items, then gradient items, each longest first
+  std::vector<SweepItem> items;   // grouped by (kind, mode), each group longest first
   std::vector<SweepReq> reqs;
-  int n_fwd = 0;
+  int group_end[4] = {0, 0, 0, 0};
   size_t o_items = 0, o_reqs = 0, o_counter = 0, total = 0;
   double pairs = 0.0;
 };
@@ -822,15 +823,20 @@ void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
   }
   std::vector<size_t> order(items.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  auto group = [&](size_t i) { return 2 * items[i].kind + P[(size_t)items[i].req].mode; };
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-    if (items[a].kind != items[b].kind) return items[a].kind < items[b].kind;
+    if (group(a) != group(b)) return group(a) < group(b);
     return cost[a] > cost[b];
   });
   L.items.resize(items.size());
-  L.n_fwd = 0;
+  int count[4] = {0, 0, 0, 0};
   for (size_t i = 0; i < order.size(); ++i) {
     L.items[i] = items[order[i]];
-    L.n_fwd += L.items[i].kind == 0 ? 1 : 0;
+    count[group(order[i])]++;
+  }
+  for (int g = 0, acc = 0; g < 4; ++g) {
+    acc += count[g];
+    L.group_end[g] = acc;
   }
   L.o_items = L.total;
   L.total += align_up(std::max<size_t>(1, L.items.size()) * sizeof(SweepItem));
@@ -853,7 +859,7 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
                            s));
     HIP_TRY(hipMemcpyAsync(base + L.o_reqs, L.reqs.data(), n * sizeof(SweepReq), hipMemcpyHostToDevice, s));
     SweepTimer tm(h, s, 2, L.pairs);
-    HIP_TRY(launch_batch_sweep(reinterpret_cast<const SweepItem*>(base + L.o_items), L.n_fwd, (int)L.items.size(),
+    HIP_TRY(launch_batch_sweep(reinterpret_cast<const SweepItem*>(base + L.o_items), L.group_end,
                                reinterpret_cast<const SweepReq*>(base + L.o_reqs),
                                reinterpret_cast<int*>(base + L.o_counter), s));
     tm.done();

@@ -51,10 +51,12 @@ constexpr float PHASE_GRID = 4096.0f;   // 2^12
 //  {kx, ky, kz, Wr}, {Wi, xi_x, xi_y, xi_z}, {|W|, arg(W) / (2 pi), 0, 0}
 constexpr int ERC = 3;
 
-// Lane-per-entry gradient sweep: VJP_J band entries per lane (entry chunks of
-// 4 waves x 64 lanes x VJP_J entries).
-constexpr int VJP_J = 8;
-constexpr int VJP_CHUNK = 256 * VJP_J;
+// Lane-per-entry gradient sweep: vjp_j(mode) band entries per lane (entry
+// chunks of 4 waves x 64 lanes x vjp_j(mode) entries); the surface mode's ten
+// accumulators leave room for fewer entries per lane at the same occupancy.
+constexpr int VJP_J_MAX = 8;
+constexpr int vjp_j(int mode) { return mode == 0 ? 6 : 8; }
+constexpr int vjp_chunk(int mode) { return 256 * vjp_j(mode); }
 // Forward sweep: FWD_J band entries per lane, FWD_CHUNK entries per block.
 constexpr int FWD_J = 4;
 constexpr int FWD_CHUNK = 256 * FWD_J;
@@ -80,9 +82,11 @@ struct SweepReq {
 constexpr int SWEEP_THREADS = 256;
 
 // ---- launchers (defined in dm_kernels.hip); all enqueue on `s` ----
-// Two persistent launches: forward items [0, n_fwd), gradient items
-// [n_fwd, n_items); counters[0..1] are zeroed first.
-hipError_t launch_batch_sweep(const SweepItem* items, int n_fwd, int n_items, const SweepReq* reqs, int* counters,
+// Up to four persistent launches over the items sorted into groups
+// (forward volume, forward surface, gradient volume, gradient surface);
+// group g is items [group_end[g-1], group_end[g]).  counters[0..3] are zeroed
+// first.
+hipError_t launch_batch_sweep(const SweepItem* items, const int* group_end, const SweepReq* reqs, int* counters,
                               hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_band_count(const GridC& g, const double* sigma6, double qmax, int32_t* cnt, int64_t n_slots,
@@ -116,7 +120,7 @@ int adjoint_blocks(const GridC& g);
 hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hipStream_t s);
 
 // Lane-per-entry gradient sweep: n_chunks blocks along the band, each covering
-// chunks_per_block x VJP_CHUNK entries, times triangle chunks of tris_per_block
+// chunks_per_block x vjp_chunk(mode) entries, times triangle chunks of tris_per_block
 // (at most VJP_TPB_MAX); same partial layout [chunk][NC][nt].
 constexpr int VJP_TPB_MAX = 512;
 hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,

@@ -908,9 +908,10 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // Lane-per-entry gradient sweep.  A block owns n_sub consecutive entry chunks
-// of VJP_CHUNK band entries (in chunk g: wave w, step j, lane l -> entry
-// 64 (w VJP_J + j) + l) and a range of at most VJP_TPB_MAX triangles, which are
-// wave-uniform.  Pairs whose nodes are too close for the closed form are
+// of vjp_chunk(MODE) band entries (in chunk g: wave w, step j, lane l -> entry
+// 64 (w J + j) + l) and a range of at most VJP_TPB_MAX strip-ordered triangles,
+// which are wave-uniform; the weighted phase factors of the two vertices a
+// triangle shares with the previous one are carried over.  Pairs whose nodes are too close for the closed form are
 // queued in LDS and evaluated by vjp_pair after each triangle, so the stable
 // branch runs on full waves instead of diverging.  Per triangle the lane sums
 // are reduced over the wave (wave_sum), over the 4 waves and
@@ -918,10 +919,135 @@ __device__ __forceinline__ float wave_sum(float v) {
 constexpr int VJP_TB = 32;   // triangles between block-level merges
 
 struct VjpLds {
-  uint16_t queue[4][64 * VJP_J];
+  uint16_t queue[4][64 * VJP_J_MAX];
   float tot[4][VJP_TB][10];
   float sum[VJP_TPB_MAX][10];
 };
+
+// Closed-form gradient pair from the phase factors of the three nodes with
+// the adjoint weight's phase folded in (G_p = e^{-2 pi i (t_p - phi_W)}) and
+// the relative phases a, b (see lag_pair for the formulas).
+template <int MODE>
+__device__ __forceinline__ void lag_pair_g(float a, float b, float amp, float G0r, float G0i, float G1r, float G1i,
+                                           float G2r, float G2i, float& wf, float z[3]) {
+  const float c = b - a;
+  const float ab = a * b;
+  const float rD = __builtin_amdgcn_rcpf(ab * c) * INV_TWO_PI_F;   // 1 / (2 pi a b c)
+  const float al = b * c * rD, be = a * c * rD, ga = ab * rD;
+  const float alw = amp * al;
+  const float k0 = -alw * be, k1 = alw * ga, k2 = -amp * (be * ga);
+  const float R0 = k0 * G0r, I0 = k0 * G0i, R1 = k1 * G1r, I1 = k1 * G1i, R2 = k2 * G2r, I2 = k2 * G2i;
+  const float s01 = al + be, s21 = ga - al, s12 = be + ga;
+  if (MODE == 0) {
+    z[0] = fmaf(-s01, I0, fmaf(-al, I1, fmaf(-be, I2, R0)));
+    z[1] = fmaf(-s21, I1, fmaf(al, I0, fmaf(-ga, I2, R1)));
+    z[2] = fmaf(s12, I2, fmaf(be, I0, fmaf(ga, I1, R2)));
+  } else {
+    wf = R0 + R1 + R2;
+    z[0] = fmaf(s01, R0, fmaf(al, R1, fmaf(be, R2, I0)));
+    z[1] = fmaf(s21, R1, fmaf(-al, R0, fmaf(ga, R2, I1)));
+    z[2] = fmaf(-s12, R2, fmaf(-be, R0, fmaf(-ga, R1, I2)));
+  }
+}
+
+// One triangle of the gradient tile: X holds the weighted phase factors of
+// vertex 1, Y of vertex 2 (computed here at a strip start); on return X holds
+// those of vertex 3, so the next triangle of the strip swaps X and Y.  Writes
+// the triangle's wave sums to L.tot[w][tt].
+template <int MODE>
+__device__ __forceinline__ void vjp_lanes_tri(const float* r, bool start, int tt, const float (&kx)[vjp_j(MODE)],
+                                              const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
+                                              const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
+                                              uint32_t vm, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
+                                              float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)],
+                                              const float4* __restrict__ erec, int64_t ew,
+                                              float tpx, float tpy, float tpz, int lane, int w, VjpLds& L) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
+  constexpr int J = vjp_j(MODE);
+  if (start) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float d2, d3;
+      rel_phases(kx[j], ky[j], kz[j], r, d2, d3);
+      const float r1 = vertex3_phase(kx[j], ky[j], kz[j], r) - d3 - phw[j];
+      const float q1 = wrap(r1), q2 = wrap(r1 + d2);
+      Xr[j] = __builtin_amdgcn_cosf(q1);
+      Xi[j] = -__builtin_amdgcn_sinf(q1);
+      Yr[j] = __builtin_amdgcn_cosf(q2);
+      Yi[j] = -__builtin_amdgcn_sinf(q2);
+    }
+  }
+  float acc[NC];
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
+  int nq = 0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    float a, b;
+    rel_phases(kx[j], ky[j], kz[j], r, a, b);
+    const float q3 = wrap(vertex3_phase(kx[j], ky[j], kz[j], r) - phw[j]);
+    const float Nr = __builtin_amdgcn_cosf(q3), Ni = -__builtin_amdgcn_sinf(q3);
+    const float c = b - a;
+    const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
+    const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
+    const bool fast = mn >= LAG_GAP && mx >= SERIES_REV;
+    float wf = 0.0f, z[3];
+    lag_pair_g<MODE>(a, b, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z);
+    if (MODE == 0) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) acc[p] += fast ? z[p] : 0.0f;
+    } else {
+      const float x0 = kx[j] * tpx, x1 = ky[j] * tpy, x2 = kz[j] * tpz;
+      acc[0] += fast ? wf : 0.0f;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const float zp = fast ? z[p] : 0.0f;
+        acc[1 + 3 * p] = fmaf(zp, x0, acc[1 + 3 * p]);
+        acc[2 + 3 * p] = fmaf(zp, x1, acc[2 + 3 * p]);
+        acc[3 + 3 * p] = fmaf(zp, x2, acc[3 + 3 * p]);
+      }
+    }
+    const bool need = !fast && ((vm >> j) & 1u);
+    const uint64_t bal = __ballot(need);
+    if (need) {
+      const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      L.queue[w][pos] = (uint16_t)((j << 6) | lane);
+    }
+    nq += __popcll(bal);
+    Xr[j] = Nr;
+    Xi[j] = Ni;
+  }
+  wave_lds_sync();
+  for (int q0 = 0; q0 < nq; q0 += 64) {
+    if (q0 + lane < nq) {
+      const int it = L.queue[w][q0 + lane];
+      const int64_t e = ew + 64 * (it >> 6) + (it & 63);
+      const float4 A = erec[ERC * e], B = erec[ERC * e + 1];
+      float tv, a, b, wf = 0.0f, z[3];
+      tri_phases(A.x, A.y, A.z, r, tv, a, b);
+      vjp_pair<MODE>(tv, a, b, A.w, B.x, wf, z);
+      if (MODE == 0) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) acc[p] += z[p];
+      } else {
+        acc[0] += wf;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          acc[1 + 3 * p] = fmaf(z[p], B.y, acc[1 + 3 * p]);
+          acc[2 + 3 * p] = fmaf(z[p], B.z, acc[2 + 3 * p]);
+          acc[3 + 3 * p] = fmaf(z[p], B.w, acc[3 + 3 * p]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch) {
+    const float v = wave_sum(acc[ch]);
+    if (lane == 0) L.tot[w][tt][ch] = v;
+  }
+  wave_lds_sync();
+}
 
 template <int MODE>
 __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, int nt, int t0, int t1,
@@ -929,15 +1055,18 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
                                                int n_sub, float tpx, float tpy, float tpz,
                                                float* __restrict__ part_out, VjpLds& L) {
   constexpr int NC = MODE == 0 ? 3 : 10;
+  constexpr int J = vjp_j(MODE);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int g = 0; g < n_sub; ++g) {
-    const int64_t ew = e_begin + (int64_t)g * VJP_CHUNK + (int64_t)w * 64 * VJP_J;
-    float kx[VJP_J], ky[VJP_J], kz[VJP_J], amp[VJP_J], phw[VJP_J];
+    const int64_t ew = e_begin + (int64_t)g * vjp_chunk(MODE) + (int64_t)w * 64 * J;
+    float kx[J], ky[J], kz[J], amp[J], phw[J];
+    float Xr[J], Xi[J], Yr[J], Yi[J];
     uint32_t vm = 0;
 #pragma unroll
-    for (int j = 0; j < VJP_J; ++j) {
+    for (int j = 0; j < J; ++j) {
       const int64_t e = ew + 64 * j + lane;
       kx[j] = ky[j] = kz[j] = amp[j] = phw[j] = 0.0f;
+      Xr[j] = Xi[j] = Yr[j] = Yi[j] = 0.0f;
       if (e < nE) {
         const float4 A = erec[ERC * e], C = erec[ERC * e + 2];
         kx[j] = A.x;
@@ -950,75 +1079,13 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
     }
     for (int tb = t0; tb < t1; tb += VJP_TB) {
       const int tn = min(VJP_TB, t1 - tb);
-      for (int tt = 0; tt < tn; ++tt) {
+      for (int tt = 0; tt < tn; tt += 2) {
         const float* r = rec + (size_t)(tb + tt) * TRI_REC;
-        float acc[NC];
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
-        int nq = 0;
-#pragma unroll
-        for (int j = 0; j < VJP_J; ++j) {
-          float tv, a, b;
-          tri_phases(kx[j], ky[j], kz[j], r, tv, a, b);
-          const float c = b - a;
-          const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
-          const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
-          const bool fast = mn >= LAG_GAP && mx >= SERIES_REV;
-          float wf = 0.0f, z[3];
-          lag_pair<MODE>(tv, a, b, amp[j], phw[j], wf, z);
-          if (MODE == 0) {
-#pragma unroll
-            for (int p = 0; p < 3; ++p) acc[p] += fast ? z[p] : 0.0f;
-          } else {
-            const float x0 = kx[j] * tpx, x1 = ky[j] * tpy, x2 = kz[j] * tpz;
-            acc[0] += fast ? wf : 0.0f;
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-              const float zp = fast ? z[p] : 0.0f;
-              acc[1 + 3 * p] = fmaf(zp, x0, acc[1 + 3 * p]);
-              acc[2 + 3 * p] = fmaf(zp, x1, acc[2 + 3 * p]);
-              acc[3 + 3 * p] = fmaf(zp, x2, acc[3 + 3 * p]);
-            }
-          }
-          const bool need = !fast && ((vm >> j) & 1u);
-          const uint64_t bal = __ballot(need);
-          if (need) {
-            const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            L.queue[w][pos] = (uint16_t)((j << 6) | lane);
-          }
-          nq += __popcll(bal);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int q0 = 0; q0 < nq; q0 += 64) {
-          if (q0 + lane < nq) {
-            const int it = L.queue[w][q0 + lane];
-            const int64_t e = ew + 64 * (it >> 6) + (it & 63);
-            const float4 A = erec[ERC * e], B = erec[ERC * e + 1];
-            float tv, a, b, wf = 0.0f, z[3];
-            tri_phases(A.x, A.y, A.z, r, tv, a, b);
-            vjp_pair<MODE>(tv, a, b, A.w, B.x, wf, z);
-            if (MODE == 0) {
-#pragma unroll
-              for (int p = 0; p < 3; ++p) acc[p] += z[p];
-            } else {
-              acc[0] += wf;
-#pragma unroll
-              for (int p = 0; p < 3; ++p) {
-                acc[1 + 3 * p] = fmaf(z[p], B.y, acc[1 + 3 * p]);
-                acc[2 + 3 * p] = fmaf(z[p], B.z, acc[2 + 3 * p]);
-                acc[3 + 3 * p] = fmaf(z[p], B.w, acc[3 + 3 * p]);
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch) {
-          const float v = wave_sum(acc[ch]);
-          if (lane == 0) L.tot[w][tt][ch] = v;
-        }
+        vjp_lanes_tri<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, vm, Xr, Xi, Yr, Yi, erec,
+                            ew, tpx, tpy, tpz, lane, w, L);
+        if (tt + 1 < tn)
+          vjp_lanes_tri<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, vm, Yr, Yi, Xr, Xi,
+                              erec, ew, tpx, tpy, tpz, lane, w, L);
       }
       __syncthreads();
       for (int i = threadIdx.x; i < tn * NC; i += SWEEP_T) {
@@ -1043,15 +1110,15 @@ __global__ void __launch_bounds__(SWEEP_T) k_vjp_lanes(GridC g, const float* __r
   __shared__ VjpLds L;
   constexpr int NC = MODE == 0 ? 3 : 10;
   const int t0 = blockIdx.y * tpb;
-  const int64_t e_begin = (int64_t)blockIdx.x * n_sub * VJP_CHUNK;
-  const int sub = (int)min<int64_t>(n_sub, (nE - e_begin + VJP_CHUNK - 1) / VJP_CHUNK);
+  const int64_t e_begin = (int64_t)blockIdx.x * n_sub * vjp_chunk(MODE);
+  const int sub = (int)min<int64_t>(n_sub, (nE - e_begin + vjp_chunk(MODE) - 1) / vjp_chunk(MODE));
   vjp_lanes_tile<MODE>(rec, nt, t0, min(nt, t0 + tpb), erec, nE, e_begin, sub, g.two_pi_over_L[0],
                        g.two_pi_over_L[1], g.two_pi_over_L[2], part + (size_t)blockIdx.x * NC * nt, L);
 }
 
 // Persistent sweeps over the work items of many independent meshes: one
-// launch for the forward tiles, one for the gradient tiles (their register
-// and LDS footprints differ, so each runs at its own occupancy).  Each
+// launch per kind of tile (forward or gradient) and density mode, since their
+// register and LDS footprints differ and each should run at its own occupancy.  Each
 // workgroup takes the next item from a global counter; every item writes its
 // own partial slot, so the results do not depend on which workgroup ran which
 // item.
@@ -1063,6 +1130,7 @@ __device__ __forceinline__ int next_item(int* counter, int* slot) {
   return it;
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(SWEEP_T) k_batch_fwd(const SweepItem* __restrict__ items, int n_items,
                                                          const SweepReq* __restrict__ reqs, int* __restrict__ counter) {
   __shared__ int slot;
@@ -1073,16 +1141,14 @@ __global__ void __launch_bounds__(SWEEP_T) k_batch_fwd(const SweepItem* __restri
     const SweepItem w = items[it];
     const SweepReq q = reqs[w.req];
     const int t0 = w.c * q.tpc, t1 = min(q.nt, t0 + q.tpc);
-    float2* row = q.fpart + (size_t)w.c * q.nE;
-    if (q.mode == 0)
-      fwd_lanes_tile<0>(q.kf, q.nE, q.rec, t0, t1, w.x0, row, L);
-    else
-      fwd_lanes_tile<1>(q.kf, q.nE, q.rec, t0, t1, w.x0, row, L);
+    fwd_lanes_tile<MODE>(q.kf, q.nE, q.rec, t0, t1, w.x0, q.fpart + (size_t)w.c * q.nE, L);
   }
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(SWEEP_T) k_batch_vjp(const SweepItem* __restrict__ items, int n_items,
                                                          const SweepReq* __restrict__ reqs, int* __restrict__ counter) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
   __shared__ int slot;
   __shared__ VjpLds L;
   for (;;) {
@@ -1091,14 +1157,10 @@ __global__ void __launch_bounds__(SWEEP_T) k_batch_vjp(const SweepItem* __restri
     const SweepItem w = items[it];
     const SweepReq q = reqs[w.req];
     const int64_t e_begin = (int64_t)w.c * q.epc;
-    const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + VJP_CHUNK - 1) / VJP_CHUNK);
+    const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + vjp_chunk(MODE) - 1) / vjp_chunk(MODE));
     const int t1 = min(q.nt, w.x0 + q.vtpb);
-    if (q.mode == 0)
-      vjp_lanes_tile<0>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
-                        q.vpart + (size_t)w.c * 3 * q.nt, L);
-    else
-      vjp_lanes_tile<1>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
-                        q.vpart + (size_t)w.c * 10 * q.nt, L);
+    vjp_lanes_tile<MODE>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
+                         q.vpart + (size_t)w.c * NC * q.nt, L);
   }
 }
 
@@ -1313,15 +1375,22 @@ hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hip
   return hipGetLastError();
 }
 
-hipError_t launch_batch_sweep(const SweepItem* items, int n_fwd, int n_items, const SweepReq* reqs, int* counters,
+hipError_t launch_batch_sweep(const SweepItem* items, const int* group_end, const SweepReq* reqs, int* counters,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(counters), (int64_t)2);
-  if (n_fwd > 0)
-    hipLaunchKernelGGL(k_batch_fwd, dim3((unsigned)std::min(n_fwd, 2048)), dim3(SWEEP_T), 0, s, items, n_fwd, reqs,
-                       counters);
-  if (n_items > n_fwd)
-    hipLaunchKernelGGL(k_batch_vjp, dim3((unsigned)std::min(n_items - n_fwd, 1280)), dim3(SWEEP_T), 0, s,
-                       items + n_fwd, n_items - n_fwd, reqs, counters + 1);
+  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(counters), (int64_t)4);
+  int begin = 0;
+  for (int grp = 0; grp < 4; ++grp) {
+    const int n = group_end[grp] - begin;
+    if (n > 0) {
+      const SweepItem* it = items + begin;
+      const dim3 blocks((unsigned)std::min(n, grp < 2 ? 2048 : 1280)), threads(SWEEP_T);
+      if (grp == 0) hipLaunchKernelGGL(k_batch_fwd<0>, blocks, threads, 0, s, it, n, reqs, counters);
+      if (grp == 1) hipLaunchKernelGGL(k_batch_fwd<1>, blocks, threads, 0, s, it, n, reqs, counters + 1);
+      if (grp == 2) hipLaunchKernelGGL(k_batch_vjp<0>, blocks, threads, 0, s, it, n, reqs, counters + 2);
+      if (grp == 3) hipLaunchKernelGGL(k_batch_vjp<1>, blocks, threads, 0, s, it, n, reqs, counters + 3);
+    }
+    begin = group_end[grp];
+  }
   return hipGetLastError();
 }
 
@@ -1329,7 +1398,7 @@ hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int 
                             int chunks_per_block, int n_chunks, const float4* erec, int64_t nE, float* part,
                             hipStream_t s) {
   if (tris_per_block < 1 || tris_per_block > VJP_TPB_MAX || chunks_per_block < 1 ||
-      (int64_t)n_chunks * chunks_per_block * VJP_CHUNK < nE)
+      (int64_t)n_chunks * chunks_per_block * vjp_chunk(mode) < nE)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_chunks, blocks_for(nt, tris_per_block));
   if (mode == 0)
