@@ -483,14 +483,16 @@ SweepPlan plan_fwd(int64_t nE, int nt) {
 }
 
 // Gradient sweep (lane per band entry): n_chunks blocks along the band of
-// sub x vjp_chunk(mode) entries each, at most 64 of them so the partials stay
-// bounded (4 B x channels x triangles x 64), times triangle chunks of tpb so
-// the grid has about VJP_TARGET_BLOCKS blocks.
+// sub x vjp_chunk(mode) entries each (one chunk per block up to 256 chunks,
+// which bounds the partials to 4 B x channels x triangles x 256), times
+// triangle chunks of tpb so the grid has about VJP_TARGET_BLOCKS blocks.
+// Each block rereads its entries' records once per chunk of triangles, so
+// long triangle ranges (few entries per block) keep that traffic low.
 SweepPlan plan_vjp(int64_t nE, int nt, int mode) {
   SweepPlan sp;
   const int64_t chunk = vjp_chunk(mode);
   const int64_t units = std::max<int64_t>(1, (nE + chunk - 1) / chunk);
-  sp.sub = (int)((units + 63) / 64);
+  sp.sub = (int)((units + 255) / 256);
   sp.n_chunks = (int)((units + sp.sub - 1) / sp.sub);
   sp.per_chunk = (int)(sp.sub * chunk);
   const int64_t want = (VJP_TARGET_BLOCKS + sp.n_chunks - 1) / sp.n_chunks;
@@ -583,7 +585,7 @@ struct ReqPlan {
 // At least 640 triangles per forward tile so small requests still give long
 // sweeps, at most 8 forward chunks so the partials of large requests stay
 // bounded (8 B x entries x 8).  Gradient items cover sub x vjp_chunk(mode) entries
-// (at most 64 chunks, as in plan_vjp) and up to VJP_TPB_MAX triangles.
+// (at most 256 chunks, as in plan_vjp) and up to VJP_TPB_MAX triangles.
 SweepPlan plan_fwd_batch(int64_t nE, int nt) {
   SweepPlan sp;
   (void)nE;
