@@ -122,7 +122,7 @@ hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hip
 // Lane-per-entry gradient sweep: n_chunks blocks along the band, each covering
 // chunks_per_block x vjp_chunk(mode) entries, times triangle chunks of tris_per_block
 // (at most VJP_TPB_MAX); same partial layout [chunk][NC][nt].
-constexpr int VJP_TPB_MAX = 512;
+constexpr int VJP_TPB_MAX = 256;
 hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,
                             int chunks_per_block, int n_chunks, const float4* erec, int64_t nE, float* part,
                             hipStream_t s);

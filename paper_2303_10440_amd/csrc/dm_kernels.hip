@@ -918,8 +918,10 @@ __device__ __forceinline__ float wave_sum(float v) {
 // then over the entry chunks, each in a fixed order, into part_out[NC][nt].
 constexpr int VJP_TB = 32;   // triangles between block-level merges
 
+constexpr int VJP_RING = 1024;   // queued pairs per wave (power of two)
+
 struct VjpLds {
-  uint16_t queue[4][64 * VJP_J_MAX];
+  uint16_t queue[4][VJP_RING];
   float tot[4][VJP_TB][10];
   float sum[VJP_TPB_MAX][10];
 };
@@ -950,19 +952,19 @@ __device__ __forceinline__ void lag_pair_g(float a, float b, float amp, float G0
   }
 }
 
-// One triangle of the gradient tile: X holds the weighted phase factors of
+// Closed-form pairs of one triangle: X holds the weighted phase factors of
 // vertex 1, Y of vertex 2 (computed here at a strip start); on return X holds
-// those of vertex 3, so the next triangle of the strip swaps X and Y.  Writes
-// the triangle's wave sums to L.tot[w][tt].
+// those of vertex 3, so the next triangle of the strip swaps X and Y.  Pairs
+// that need the stable scheme are appended to the wave's ring of queued pairs
+// (ring positions tail.., tagged with the triangle's parity).
 template <int MODE>
-__device__ __forceinline__ void vjp_lanes_tri(const float* r, bool start, int tt, const float (&kx)[vjp_j(MODE)],
-                                              const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
-                                              const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
-                                              uint32_t vm, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
-                                              float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)],
-                                              const float4* __restrict__ erec, int64_t ew,
-                                              float tpx, float tpy, float tpz, int lane, int w, VjpLds& L) {
-  constexpr int NC = MODE == 0 ? 3 : 10;
+__device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int tag, const float (&kx)[vjp_j(MODE)],
+                                               const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
+                                               const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
+                                               uint32_t vm, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
+                                               float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)], float tpx,
+                                               float tpy, float tpz, int lane, uint16_t* ring, int& tail,
+                                               float (&acc)[MODE == 0 ? 3 : 10]) {
   constexpr int J = vjp_j(MODE);
   if (start) {
 #pragma unroll
@@ -977,10 +979,6 @@ __device__ __forceinline__ void vjp_lanes_tri(const float* r, bool start, int tt
       Yi[j] = -__builtin_amdgcn_sinf(q2);
     }
   }
-  float acc[NC];
-#pragma unroll
-  for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
-  int nq = 0;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     float a, b;
@@ -1010,43 +1008,108 @@ __device__ __forceinline__ void vjp_lanes_tri(const float* r, bool start, int tt
     const bool need = !fast && ((vm >> j) & 1u);
     const uint64_t bal = __ballot(need);
     if (need) {
-      const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      L.queue[w][pos] = (uint16_t)((j << 6) | lane);
+      const int pos = tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      ring[pos & (VJP_RING - 1)] = (uint16_t)((tag << 9) | (j << 6) | lane);
     }
-    nq += __popcll(bal);
+    tail += __popcll(bal);
     Xr[j] = Nr;
     Xi[j] = Ni;
   }
+}
+
+// Stable scheme for n queued pairs from ring position head, on full waves:
+// pairs tagged cur_tag belong to triangle r_cur (sums into acc_cur), the others
+// to the previous triangle r_prev (acc_prev).
+template <int MODE>
+__device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, int n, const float* r_cur,
+                                               const float* r_prev, int cur_tag, const float4* __restrict__ erec,
+                                               int64_t ew, int lane, float (&acc_cur)[MODE == 0 ? 3 : 10],
+                                               float (&acc_prev)[MODE == 0 ? 3 : 10]) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
   wave_lds_sync();
-  for (int q0 = 0; q0 < nq; q0 += 64) {
-    if (q0 + lane < nq) {
-      const int it = L.queue[w][q0 + lane];
-      const int64_t e = ew + 64 * (it >> 6) + (it & 63);
-      const float4 A = erec[ERC * e], B = erec[ERC * e + 1];
-      float tv, a, b, wf = 0.0f, z[3];
-      tri_phases(A.x, A.y, A.z, r, tv, a, b);
-      vjp_pair<MODE>(tv, a, b, A.w, B.x, wf, z);
-      if (MODE == 0) {
+  if (lane < n) {
+    const int it = ring[(head + lane) & (VJP_RING - 1)];
+    const bool cur = (it >> 9) == cur_tag;
+    const float* r = cur ? r_cur : r_prev;
+    const int64_t e = ew + 64 * ((it >> 6) & 7) + (it & 63);
+    const float4 A = erec[ERC * e], B = erec[ERC * e + 1];
+    float tv, a, b, wf = 0.0f, z[3];
+    tri_phases(A.x, A.y, A.z, r, tv, a, b);
+    vjp_pair<MODE>(tv, a, b, A.w, B.x, wf, z);
+    float add[NC];
+    if (MODE == 0) {
 #pragma unroll
-        for (int p = 0; p < 3; ++p) acc[p] += z[p];
-      } else {
-        acc[0] += wf;
+      for (int p = 0; p < 3; ++p) add[p] = z[p];
+    } else {
+      add[0] = wf;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-          acc[1 + 3 * p] = fmaf(z[p], B.y, acc[1 + 3 * p]);
-          acc[2 + 3 * p] = fmaf(z[p], B.z, acc[2 + 3 * p]);
-          acc[3 + 3 * p] = fmaf(z[p], B.w, acc[3 + 3 * p]);
-        }
+      for (int p = 0; p < 3; ++p) {
+        add[1 + 3 * p] = z[p] * B.y;
+        add[2 + 3 * p] = z[p] * B.z;
+        add[3 + 3 * p] = z[p] * B.w;
       }
     }
-  }
 #pragma unroll
-  for (int ch = 0; ch < NC; ++ch) {
+    for (int ch = 0; ch < NC; ++ch) {
+      acc_cur[ch] += cur ? add[ch] : 0.0f;
+      acc_prev[ch] += cur ? 0.0f : add[ch];
+    }
+  }
+}
+
+// Wave sums of one triangle into L.tot[w][tt].
+template <int MODE>
+__device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3 : 10], int tt, int lane, int w,
+                                                VjpLds& L) {
+#pragma unroll
+  for (int ch = 0; ch < (MODE == 0 ? 3 : 10); ++ch) {
     const float v = wave_sum(acc[ch]);
     if (lane == 0) L.tot[w][tt][ch] = v;
   }
-  wave_lds_sync();
+}
+
+// One triangle with the queue bookkeeping: full passes whenever 64 pairs are
+// queued; the previous triangle (at most one other is open) is finished by a
+// partial pass only if some of its pairs are still queued, so most passes are
+// full.  A triangle is closed (reduced into L.tot) once none of its pairs is
+// queued.
+template <int MODE>
+__device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int tt, const float (&kx)[vjp_j(MODE)],
+                                               const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
+                                               const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
+                                               uint32_t vm, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
+                                               float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)],
+                                               const float4* __restrict__ erec, int64_t ew, float tpx, float tpy,
+                                               float tpz, int lane, int w, VjpLds& L, int& head, int& tail,
+                                               bool& prev_open, int& prev_end, const float*& r_prev,
+                                               float (&acc_prev)[MODE == 0 ? 3 : 10]) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
+  float acc[NC];
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
+  const int tag = tt & 1;
+  vjp_lanes_main<MODE>(r, start, tag, kx, ky, kz, amp, phw, vm, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w], tail,
+                       acc);
+  while (tail - head >= 64) {
+    vjp_lanes_pass<MODE>(L.queue[w], head, 64, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+    head += 64;
+  }
+  if (prev_open && head < prev_end) {
+    vjp_lanes_pass<MODE>(L.queue[w], head, tail - head, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+    head = tail;
+  }
+  if (prev_open) vjp_lanes_close<MODE>(acc_prev, tt - 1, lane, w, L);
+  if (head == tail) {
+    vjp_lanes_close<MODE>(acc, tt, lane, w, L);
+    prev_open = false;
+  } else {
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) acc_prev[ch] = acc[ch];
+    prev_open = true;
+    prev_end = tail;
+    r_prev = r;
+  }
 }
 
 template <int MODE>
@@ -1079,13 +1142,28 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
     }
     for (int tb = t0; tb < t1; tb += VJP_TB) {
       const int tn = min(VJP_TB, t1 - tb);
+      int head = 0, tail = 0, prev_end = 0;
+      bool prev_open = false;
+      const float* r_prev = rec + (size_t)tb * TRI_REC;
+      float acc_prev[NC];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) acc_prev[ch] = 0.0f;
       for (int tt = 0; tt < tn; tt += 2) {
         const float* r = rec + (size_t)(tb + tt) * TRI_REC;
-        vjp_lanes_tri<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, vm, Xr, Xi, Yr, Yi, erec,
-                            ew, tpx, tpy, tpz, lane, w, L);
+        vjp_lanes_step<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, vm, Xr, Xi, Yr, Yi, erec, ew,
+                             tpx, tpy, tpz, lane, w, L, head, tail, prev_open, prev_end, r_prev, acc_prev);
         if (tt + 1 < tn)
-          vjp_lanes_tri<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, vm, Yr, Yi, Xr, Xi,
-                              erec, ew, tpx, tpy, tpz, lane, w, L);
+          vjp_lanes_step<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, vm, Yr, Yi, Xr, Xi,
+                               erec, ew, tpx, tpy, tpz, lane, w, L, head, tail, prev_open, prev_end, r_prev,
+                               acc_prev);
+      }
+      if (prev_open) {
+        // only the last triangle (tn - 1) is still open: finish its pairs
+        float none[NC];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) none[ch] = 0.0f;
+        vjp_lanes_pass<MODE>(L.queue[w], head, tail - head, r_prev, r_prev, (tn & 1), erec, ew, lane, none, acc_prev);
+        vjp_lanes_close<MODE>(acc_prev, tn - 1, lane, w, L);
       }
       __syncthreads();
       for (int i = threadIdx.x; i < tn * NC; i += SWEEP_T) {
