@@ -55,11 +55,12 @@ constexpr int ERC = 3;
 // chunks of 4 waves x 64 lanes x vjp_j(mode) entries); the surface mode's ten
 // accumulators leave room for fewer entries per lane at the same occupancy.
 constexpr int VJP_J_MAX = 8;
-constexpr int vjp_j(int mode) { return mode == 0 ? 6 : 8; }
+constexpr int vjp_j(int mode) { return mode == 0 ? 5 : 8; }
 constexpr int vjp_chunk(int mode) { return 256 * vjp_j(mode); }
 // Forward sweep: FWD_J band entries per lane, FWD_CHUNK entries per block.
-constexpr int FWD_J = 4;
+constexpr int FWD_J = 3;
 constexpr int FWD_CHUNK = 256 * FWD_J;
+static_assert(FWD_J <= 8 && VJP_J_MAX <= 8, "queued pairs store the entry step in 3 bits");
 
 // Work item of the persistent batched sweeps: one tile of one request's
 // forward sweep (kind 0: FWD_CHUNK band entries from x0, triangle chunk c) or

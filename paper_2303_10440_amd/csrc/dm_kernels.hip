@@ -633,7 +633,7 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
     if (need) {
       const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      queue[pos] = (uint16_t)((tag << 8) | (j << 6) | lane);
+      queue[pos] = (uint16_t)((tag << 9) | (j << 6) | lane);
     }
     nq += __popcll(bal);
     Xr[j] = Nr;
@@ -659,8 +659,8 @@ __device__ __forceinline__ void fwd_lanes_flush(const float* r, const float4* __
     float fr = 0.0f, fi = 0.0f;
     if (act) {
       const int it = L.queue[w][q0 + lane];
-      p = it >> 8;
-      jj = (it >> 6) & 3;
+      p = it >> 9;
+      jj = (it >> 6) & 7;
       ll = it & 63;
       const float* rp = r + (size_t)p * TRI_REC;
       const float4 k = kf[ew + 64 * jj + ll];
