@@ -50,7 +50,16 @@ ALG = {
 # divided by what the same counter reads for a plain device-to-device copy of
 # known size.  Valid only for the kernel source it was measured on: if the
 # hash of the kernel file differs, the benchmark reports traffic as null.
-TRAFFIC = None
+TRAFFIC = {
+    "kernel": "k_vjp_lanes<0>",
+    "source_sha256": "38b85cbc20aee2406e8967c3520dcc4906655258d2dc24a171de9222fa03c46a",
+    # FETCH_SIZE 2,451,903 KiB x 2.000 (a 256 MiB copy reads 131,089 KiB) and
+    # WRITE_SIZE 14,331 KiB x 1.000 (the copy writes 262,144 KiB), per launch
+    "read_bytes": 2451903.4 * 1024 * 2.0,
+    "write_bytes": 14331.1 * 1024 * 1.0,
+    "profile": "profiles/k_vjp_lanes_cfg3_volume.md",
+}
+TRAFFIC["bytes_per_launch"] = TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
 
 
 def kernel_source_sha256() -> str:
