@@ -1224,9 +1224,12 @@ __global__ void __launch_bounds__(SWEEP_T) k_batch_fwd(const SweepItem* __restri
   }
 }
 
+// The item loop around the tile must not cost occupancy: at least as many
+// waves per SIMD as the single-request gradient sweep (5 volume, 3 surface).
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_batch_vjp(const SweepItem* __restrict__ items, int n_items,
-                                                         const SweepReq* __restrict__ reqs, int* __restrict__ counter) {
+__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3)
+    k_batch_vjp(const SweepItem* __restrict__ items, int n_items, const SweepReq* __restrict__ reqs,
+                int* __restrict__ counter) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   __shared__ int slot;
   __shared__ VjpLds L;
