@@ -129,6 +129,21 @@ dm_status dm_topology_destroy(dm_topology* t);
 /* closed = 1 if closed and consistently oriented. */
 dm_status dm_topology_info(const dm_topology* t, int32_t* n_faces, int32_t* n_verts, int32_t* closed);
 
+/* The triangle order a topology uses internally, computed on the host (no
+ * device needed): greedy triangle strips, in which every triangle after the
+ * first of a strip shares the edge formed by the previous triangle's last two
+ * vertices and so adds one vertex.  The mesh transform is a sum over
+ * triangles (Eq. 5, and the volume form of the indicator), so the order only
+ * changes rounding; the sweeps use it to share vertex phase factors.
+ * faces: [n_faces][3] host array (indices are not checked here).
+ * faces_out: [n_faces][3] host array, the faces in strip order, each written
+ * as (s_i, s_i+1, s_i+2).  flags_out: [n_faces] host array, bit 0 = first
+ * triangle of a strip, bit 1 = the written vertex order is an odd
+ * permutation of the input face (opposite orientation).  n_strips may be NULL.
+ * DM_ERR_ARG for a negative count or NULL arrays with n_faces > 0. */
+dm_status dm_topology_strips(const int32_t* faces, int32_t n_faces, int32_t* faces_out, int32_t* flags_out,
+                             int32_t* n_strips);
+
 /* ------------------------------------------------------------------ band */
 
 /* Number of frequency entries evaluated for (grid, psf): the in-band

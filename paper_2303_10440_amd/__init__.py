@@ -104,6 +104,7 @@ def _load():
         "dm_topology_create": [vp, vp, i32, i32, ctypes.c_int, ctypes.POINTER(vp)],
         "dm_topology_destroy": [vp],
         "dm_topology_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "dm_topology_strips": [vp, i32, vp, vp, ctypes.POINTER(i32)],
         "dm_band_size": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), ctypes.POINTER(i64), vp],
         "dm_band_export": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), vp, vp, vp, vp],
         "dm_render": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CPsf), ctypes.POINTER(CGrid), vp, vp, vp],
@@ -297,6 +298,19 @@ def _mesh(verts, topo: Topology) -> CMesh:
 
 
 # ----------------------------------------------------------------- calls
+def topology_strips(faces):
+    """The strip order a topology uses (host only): (faces [n,3] int32 in strip
+    order, flags [n] int32 (bit 0 strip start, bit 1 reversed orientation),
+    number of strips)."""
+    F = np.ascontiguousarray(np.asarray(faces, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros_like(F)
+    flags = np.zeros(len(F), np.int32)
+    ns = ctypes.c_int32()
+    _check(_load().dm_topology_strips(ctypes.c_void_p(F.ctypes.data), len(F), ctypes.c_void_p(out.ctypes.data),
+                                      ctypes.c_void_p(flags.ctypes.data), ctypes.byref(ns)), "dm_topology_strips")
+    return out, flags, int(ns.value)
+
+
 def band_size(h: Handle, grid, sigma6) -> int:
     n = ctypes.c_int64()
     g, p = _grid(grid), _psf(sigma6)

@@ -1032,6 +1032,22 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
   return DM_OK;
 }
 
+dm_status dm_topology_strips(const int32_t* faces, int32_t n_faces, int32_t* faces_out, int32_t* flags_out,
+                             int32_t* n_strips) {
+  g_err.clear();
+  if (n_faces < 0) return fail(DM_ERR_ARG, "negative face count");
+  if (n_faces > 0 && (!faces || !faces_out || !flags_out)) return fail(DM_ERR_ARG, "NULL array");
+  if ((int64_t)n_faces * 3 >= ((int64_t)1 << 31)) return fail(DM_ERR_ARG, "too many faces");
+  std::vector<int32_t> F(faces, faces + (size_t)n_faces * 3), Fs, fl;
+  const int ns = build_strips(F, Fs, fl);
+  if (n_faces > 0) {
+    memcpy(faces_out, Fs.data(), Fs.size() * sizeof(int32_t));
+    memcpy(flags_out, fl.data(), fl.size() * sizeof(int32_t));
+  }
+  if (n_strips) *n_strips = ns;
+  return DM_OK;
+}
+
 dm_status dm_topology_destroy(dm_topology* t) {
   g_err.clear();
   if (!t) return DM_OK;

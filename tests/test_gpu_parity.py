@@ -155,6 +155,39 @@ def test_render_image_and_spectrum(dm, handle, ref, name, mode):
     assert abs(total - dc) < 1e-5 * abs(dc)
 
 
+def _surface_only_case(name):
+    """Meshes only the surface density accepts: an open hemisphere (boundary
+    edges, unused vertices) and a box with a fin (an edge shared by three
+    faces)."""
+    if name == "hemisphere":
+        c = configs.cfg1(SURFACE)
+        U, F = meshes.icosphere(2)
+        F = F[U[F].mean(axis=1)[:, 2] > 0.1]
+        return configs.Case("hemisphere", c.V, F.astype(np.int32), c.grid, c.sigma)
+    box = configs.box_case(mode=SURFACE)
+    V = np.concatenate([box.V, [[15.0, 25.0, 16.0]]]).astype(np.float32)
+    F = np.concatenate([box.F, [[box.F[0][0], box.F[0][1], len(box.V)]]]).astype(np.int32)
+    return configs.Case("fin", V, F, box.grid, box.sigma)
+
+
+@pytest.mark.parametrize("name", ["hemisphere", "fin"])
+def test_surface_open_and_nonmanifold_meshes(dm, handle, ref, name):
+    say("surface", name)
+    c = _surface_only_case(name)
+    V, F, g, S = prepared(c, SURFACE)
+    topo = handle.topology(F, n_verts=len(V))
+    img = dm.render(handle, dev(V), topo, S, g).cpu().numpy().astype(np.float64)
+    want = ref.render(V.astype(np.float64), F, g, S)
+    say("  rel err image", rel_l2(img, want))
+    assert rel_l2(img, want) < IMG_TOL
+    G = np.random.default_rng(12).standard_normal(g.n).astype(np.float32)
+    dv, ds, _ = dm.render_vjp(handle, dev(V), topo, S, g, dev(G))
+    dvw, dsw = ref.render_vjp(V.astype(np.float64), F, g, S, G.astype(np.float64))
+    say("  rel err dV", rel_l2(dv.cpu().numpy(), dvw), "dSigma", rel_l2(ds.cpu().numpy(), dsw))
+    assert rel_l2(dv.cpu().numpy(), dvw) < GRAD_TOL
+    assert rel_l2(ds.cpu().numpy(), dsw) < GRAD_TOL
+
+
 def test_render_empty_band_gives_zero_image(dm, handle, ref):
     say("render empty band")
     c = configs.cfg1()
