@@ -157,20 +157,29 @@ def test_render_image_and_spectrum(dm, handle, ref, name, mode):
 
 def _surface_only_case(name):
     """Meshes only the surface density accepts: an open hemisphere (boundary
-    edges, unused vertices) and a box with a fin (an edge shared by three
-    faces)."""
+    edges, unused vertices), a box with a fin (an edge shared by three faces)
+    and a sphere with two zero-area triangles (which add nothing)."""
     if name == "hemisphere":
         c = configs.cfg1(SURFACE)
         U, F = meshes.icosphere(2)
         F = F[U[F].mean(axis=1)[:, 2] > 0.1]
         return configs.Case("hemisphere", c.V, F.astype(np.int32), c.grid, c.sigma)
+    if name == "degenerate":
+        # zero-area triangles: a repeated vertex, and three points on one
+        # axis-aligned line (collinear exactly, in float32 and in float64)
+        c = configs.cfg1(SURFACE)
+        n = len(c.V)
+        line = [[10.0, 12.5, 14.0], [11.5, 12.5, 14.0], [13.25, 12.5, 14.0]]
+        V = np.concatenate([c.V, line]).astype(np.float32)
+        F = np.concatenate([c.F, [[0, 0, 1], [n, n + 1, n + 2]]]).astype(np.int32)
+        return configs.Case("degenerate", V, F, c.grid, c.sigma)
     box = configs.box_case(mode=SURFACE)
     V = np.concatenate([box.V, [[15.0, 25.0, 16.0]]]).astype(np.float32)
     F = np.concatenate([box.F, [[box.F[0][0], box.F[0][1], len(box.V)]]]).astype(np.int32)
     return configs.Case("fin", V, F, box.grid, box.sigma)
 
 
-@pytest.mark.parametrize("name", ["hemisphere", "fin"])
+@pytest.mark.parametrize("name", ["hemisphere", "fin", "degenerate"])
 def test_surface_open_and_nonmanifold_meshes(dm, handle, ref, name):
     say("surface", name)
     c = _surface_only_case(name)
