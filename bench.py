@@ -16,6 +16,7 @@ Prints ONE JSON line.  Synthetic data (seeded); no dataset.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -157,6 +158,50 @@ def bench_batch(dm, h, reps: int = 2) -> dict:
             "looped_pairs_per_s": pairs / (tl * 1e-3), "speedup": tl / tb, "max_image_rel_diff": worst}
 
 
+def bench_fit(dm, h, case, mode, shape_steps: int = 10, psf_steps: int = 4) -> dict:
+    """Staggered fitting on the single-cell workload: the target is the cell
+    rendered with sigma (0.15, 0.15, 0.45) um; the fit starts from the cell
+    shrunk by 3% about its centroid and a PSF 20% too wide, and times shape
+    steps (narrow band, weighted L2, Adam on the vertices) and PSF steps
+    (full spectrum, plain L2, Adam on (sigma_xy, sigma_z))."""
+    import torch
+    from paper_2303_10440_amd import fit
+    g = case.grid
+    s_xy, s_z = float(np.sqrt(case.sigma[0])), float(np.sqrt(case.sigma[2]))
+    dev = torch.device("cuda:0")
+    topo = h.topology(case.F, n_verts=len(case.V))
+    target = dm.render(h, torch.tensor(case.V, device=dev), topo, case.sigma, g)
+    c = case.V.mean(0)
+    V = torch.tensor((c + 0.97 * (case.V - c)).astype(np.float32), device=dev)
+    F = fit.StaggeredFit(h, topo, V, 1.2 * s_xy, 1.2 * s_z, g, target,
+                         fit.FitConfig(lr_shape=0.005, lr_psf=0.005))
+    F.shape_step()
+    F.psf_step()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(s)
+    for _ in range(shape_steps):
+        F.shape_step()
+    e1.record(s)
+    for _ in range(psf_steps):
+        F.psf_step()
+    e2.record(s)
+    torch.cuda.synchronize()
+    n_band = float(dm.band_size(h, g, case.sigma))
+    n_full = float(dm.band_size(h, dataclasses.replace(g, tau=0.0), case.sigma))
+    ts, tp = e0.elapsed_time(e1) / shape_steps, e1.elapsed_time(e2) / psf_steps
+    losses = [l for k, l in F.history]
+    return {"workload": "single-cell fit: shape steps on the band OTF > 1e-3, PSF steps on the full "
+                        "spectrum (tau = 0), start 3% shrunk and PSF 20% wide",
+            "shape_step_ms": ts, "psf_step_ms": tp,
+            "shape_pairs_per_s": n_band * case.F.shape[0] / (ts * 1e-3),
+            "psf_pairs_per_s": n_full * case.F.shape[0] / (tp * 1e-3),
+            "band_entries": n_band, "full_spectrum_entries": n_full,
+            "first_shape_loss": losses[0], "last_shape_loss": [l for k, l in F.history if k == "shape"][-1],
+            "psf": [float(x) for x in F.psf]}
+
+
 def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_inflight: int, pool: int = 32,
                 seed: int = 0) -> dict:
     """cfg5: Poisson arrivals of forward + gradient requests on resident cells
@@ -226,6 +271,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", action="store_true", help="add the 64-cell batched vs looped comparison")
+    ap.add_argument("--fit", action="store_true",
+                    help="add the staggered shape / PSF fitting steps on the single-cell workload")
     ap.add_argument("--serve", type=float, nargs="*", default=None,
                     help="add the serving comparison at these arrival rates (req/s)")
     ap.add_argument("--serve-count", type=int, default=200)
@@ -295,7 +342,7 @@ def main() -> int:
     dms = (fwd_ms if dom == "fwd" else vjp_ms) / max(launches, 1)
     per_launch_pairs = (fwd_pairs if dom == "fwd" else vjp_pairs) / max(launches, 1)
     achieved = per_launch_pairs * flop_eq(dkind) / (dms * 1e-3) / 1e12
-    kname = ("k_fwd_sweep" if dom == "fwd" else "k_vjp_lanes") + ("<0>" if mode == configs.VOLUME else "<1>")
+    kname = ("k_fwd_lanes" if dom == "fwd" else "k_vjp_lanes") + ("<0>" if mode == configs.VOLUME else "<1>")
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(kname),
                 "kernel": kname,
@@ -333,6 +380,8 @@ def main() -> int:
         out["copy_calibration_bytes"] = 256 << 20
     if args.batch:
         out["batched"] = bench_batch(dm, h)
+    if args.fit:
+        out["fit"] = bench_fit(dm, h, case, mode)
     if args.serve is not None:
         out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:
