@@ -53,10 +53,10 @@ ALG = {
 # hash of the kernel file differs, the benchmark reports traffic as null.
 TRAFFIC = {
     "kernel": "k_vjp_lanes<0>",
-    "source_sha256": "38b85cbc20aee2406e8967c3520dcc4906655258d2dc24a171de9222fa03c46a",
-    # FETCH_SIZE 2,451,903 KiB x 2.000 (a 256 MiB copy reads 131,089 KiB) and
+    "source_sha256": "086ce461a18da5eb2a479bba5c0278d87255a1759d5f43ea27155f2d5ca2ca40",
+    # FETCH_SIZE 2,452,689 KiB x 2.000 (a 256 MiB copy reads 131,089 KiB) and
     # WRITE_SIZE 14,331 KiB x 1.000 (the copy writes 262,144 KiB), per launch
-    "read_bytes": 2451903.4 * 1024 * 2.0,
+    "read_bytes": 2452689.4 * 1024 * 2.0,
     "write_bytes": 14331.1 * 1024 * 1.0,
     "profile": "profiles/k_vjp_lanes_cfg3_volume.md",
 }
