@@ -524,7 +524,7 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
                          sgn * (e2[0] * e3[1] - e2[1] * e3[0])};
     const double twoA = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     if (MODE == 0) {
-      for (int j = 0; j < 3; ++j) r[12 + j] = (float)(n[j] / g.L[j]);
+      for (int j = 0; j < 3; ++j) r[12 + j] = (float)(n[j] / (g.L[j] * TWO_PI_D * TWO_PI_D));
     } else {
       r[12] = (float)twoA;
       r[13] = 0.0f;
@@ -576,6 +576,7 @@ constexpr int SWEEP_T = 256;
 // entry and are added to the register sums at the end.
 constexpr float FWD_LAG_GAP = 0.005f;
 constexpr float INV_4PI2_F = 0.025330295910584444f;   // 1 / (4 pi^2)
+constexpr float FOUR_PI2_F = 39.47841760435743f;       // 4 pi^2
 constexpr int FWD_TQ = 4;   // triangles whose queued pairs share one pass
 
 // Queued pairs of FWD_TQ consecutive triangles share one pass.  Within a pass
@@ -604,26 +605,27 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
       float d2, d3;
       rel_phases(kx[j], ky[j], kz[j], r, d2, d3);
       const float t1 = vertex3_phase(kx[j], ky[j], kz[j], r) - d3;
-      const float q1 = wrap(t1), q2 = wrap(t1 + d2);
+      const float q1 = wrap(-t1), q2 = wrap(-(t1 + d2));
       Xr[j] = __builtin_amdgcn_cosf(q1);
-      Xi[j] = -__builtin_amdgcn_sinf(q1);
+      Xi[j] = __builtin_amdgcn_sinf(q1);
       Yr[j] = __builtin_amdgcn_cosf(q2);
-      Yi[j] = -__builtin_amdgcn_sinf(q2);
+      Yi[j] = __builtin_amdgcn_sinf(q2);
     }
   }
 #pragma unroll
   for (int j = 0; j < FWD_J; ++j) {
     float a, b;
     rel_phases(kx[j], ky[j], kz[j], r, a, b);
-    const float q3 = wrap(vertex3_phase(kx[j], ky[j], kz[j], r));
-    const float Nr = __builtin_amdgcn_cosf(q3), Ni = -__builtin_amdgcn_sinf(q3);
+    // e^{-2 pi i t} = (cos 2 pi q, sin 2 pi q) at q = -t: no negation of the sine
+    const float q3 = wrap(-vertex3_phase(kx[j], ky[j], kz[j], r));
+    const float Nr = __builtin_amdgcn_cosf(q3), Ni = __builtin_amdgcn_sinf(q3);
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
     const bool fast = mn >= FWD_LAG_GAP && mx >= SERIES_REV;
-    const float wt = MODE == 0 ? fmaf(kz[j], r[14], fmaf(ky[j], r[13], kx[j] * r[12])) : r[12];
-    const float kap = wt * __builtin_amdgcn_rcpf(fast ? a * b * c : 1.0f) * INV_4PI2_F;
-    const float kk = fast ? kap : 0.0f;
+    // the volume weight k.n carries the 1 / (4 pi^2) of the record's normal
+    const float wt = MODE == 0 ? fmaf(kz[j], r[14], fmaf(ky[j], r[13], kx[j] * r[12])) : r[12] * INV_4PI2_F;
+    const float kk = fast ? wt * __builtin_amdgcn_rcpf(a * b * c) : 0.0f;
     const float tr = fmaf(-c, Xr[j], fmaf(b, Yr[j], -a * Nr));
     const float ti = fmaf(-c, Xi[j], fmaf(b, Yi[j], -a * Ni));
     ar[j] = fmaf(kk, tr, ar[j]);
@@ -666,7 +668,7 @@ __device__ __forceinline__ void fwd_lanes_flush(const float* r, const float4* __
       const float4 k = kf[ew + 64 * jj + ll];
       float t1, d2, d3;
       tri_phases(k.x, k.y, k.z, rp, t1, d2, d3);
-      const float wt = MODE == 0 ? fmaf(k.z, rp[14], fmaf(k.y, rp[13], k.x * rp[12])) : rp[12];
+      const float wt = MODE == 0 ? fmaf(k.z, rp[14], fmaf(k.y, rp[13], k.x * rp[12])) * FOUR_PI2_F : rp[12];
       dd3_acc(t1, d2, d3, wt, fr, fi);
     }
 #pragma unroll
@@ -929,13 +931,15 @@ struct VjpLds {
 
 // Closed-form gradient pair from the phase factors of the three nodes with
 // the adjoint weight's phase folded in (G_p = e^{-2 pi i (t_p - phi_W)}) and
-// the relative phases a, b (see lag_pair for the formulas).
+// the relative phases a, b (see lag_pair for the formulas).  With use false
+// every output is exactly zero (the common factor 1 / (2 pi a b c) is
+// replaced by zero, so a vanishing gap cannot produce inf or NaN).
 template <int MODE>
-__device__ __forceinline__ void lag_pair_g(float a, float b, float amp, float G0r, float G0i, float G1r, float G1i,
-                                           float G2r, float G2i, float& wf, float z[3]) {
+__device__ __forceinline__ void lag_pair_g(float a, float b, bool use, float amp, float G0r, float G0i, float G1r,
+                                           float G1i, float G2r, float G2i, float& wf, float z[3]) {
   const float c = b - a;
   const float ab = a * b;
-  const float rD = __builtin_amdgcn_rcpf(ab * c) * INV_TWO_PI_F;   // 1 / (2 pi a b c)
+  const float rD = use ? __builtin_amdgcn_rcpf(ab * c) * INV_TWO_PI_F : 0.0f;   // 1 / (2 pi a b c)
   const float al = b * c * rD, be = a * c * rD, ga = ab * rD;
   const float alw = amp * al;
   const float k0 = -alw * be, k1 = alw * ga, k2 = -amp * (be * ga);
@@ -973,34 +977,34 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
       float d2, d3;
       rel_phases(kx[j], ky[j], kz[j], r, d2, d3);
       const float r1 = vertex3_phase(kx[j], ky[j], kz[j], r) - d3 - phw[j];
-      const float q1 = wrap(r1), q2 = wrap(r1 + d2);
+      const float q1 = wrap(-r1), q2 = wrap(-(r1 + d2));
       Xr[j] = __builtin_amdgcn_cosf(q1);
-      Xi[j] = -__builtin_amdgcn_sinf(q1);
+      Xi[j] = __builtin_amdgcn_sinf(q1);
       Yr[j] = __builtin_amdgcn_cosf(q2);
-      Yi[j] = -__builtin_amdgcn_sinf(q2);
+      Yi[j] = __builtin_amdgcn_sinf(q2);
     }
   }
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     float a, b;
     rel_phases(kx[j], ky[j], kz[j], r, a, b);
-    const float q3 = wrap(vertex3_phase(kx[j], ky[j], kz[j], r) - phw[j]);
-    const float Nr = __builtin_amdgcn_cosf(q3), Ni = -__builtin_amdgcn_sinf(q3);
+    const float q3 = wrap(phw[j] - vertex3_phase(kx[j], ky[j], kz[j], r));
+    const float Nr = __builtin_amdgcn_cosf(q3), Ni = __builtin_amdgcn_sinf(q3);
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
     const bool fast = mn >= LAG_GAP && mx >= SERIES_REV;
     float wf = 0.0f, z[3];
-    lag_pair_g<MODE>(a, b, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z);
+    lag_pair_g<MODE>(a, b, fast, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z);
     if (MODE == 0) {
 #pragma unroll
-      for (int p = 0; p < 3; ++p) acc[p] += fast ? z[p] : 0.0f;
+      for (int p = 0; p < 3; ++p) acc[p] += z[p];
     } else {
       const float x0 = kx[j] * tpx, x1 = ky[j] * tpy, x2 = kz[j] * tpz;
-      acc[0] += fast ? wf : 0.0f;
+      acc[0] += wf;
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
-        const float zp = fast ? z[p] : 0.0f;
+        const float zp = z[p];
         acc[1 + 3 * p] = fmaf(zp, x0, acc[1 + 3 * p]);
         acc[2 + 3 * p] = fmaf(zp, x1, acc[2 + 3 * p]);
         acc[3 + 3 * p] = fmaf(zp, x2, acc[3 + 3 * p]);
@@ -1182,8 +1186,10 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
   }
 }
 
+// At most 96 VGPRs in volume mode: 5 waves per SIMD (one more register
+// granule would leave 4).
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_vjp_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb,
+__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3) k_vjp_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb,
                                                          const float4* __restrict__ erec, int64_t nE, int n_sub,
                                                          float* __restrict__ part) {
   __shared__ VjpLds L;
