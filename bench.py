@@ -30,19 +30,20 @@ if ROOT not in sys.path:
 
 METRIC = "tri·freq pairs/s fwd+VJP (5k tris, 128²×64) vs plain; p50/p99 render latency"
 
-# Peak of the FP32 vector ALU of one MI355X: 256 CUs x 4 SIMDs x 32 lanes x
-# 2 flops (FMA) x 2.4 GHz = 157.3 TFLOP/s.  Transcendentals (v_sin, v_cos,
-# v_rcp) issue at a quarter of the FMA rate, so one costs the issue slots of
-# 4 FMAs = 8 flops.
+# Published peak of the FP32 vector ALU of one MI355X: 256 CUs x 4 SIMDs x
+# 32 lanes x 2 flops (FMA) x 2.4 GHz = 157.3 TFLOP/s.
 PEAK_TFLOPS = 157.3
-TRANS_FLOP_EQ = 8.0
+TRANS_KINDS = ("sin", "cos", "rcp")
 # Algorithmic work per frequency-triangle pair, counted from the closed forms
-# (Eq. 7-8 forward; Eq. 9-10 and the indicator shape derivative for the
-# gradient): FP32 flops (FMA = 2) and transcendentals.
+# as written (Eq. 7-8 forward: three vertex phase factors and one reciprocal;
+# Eq. 9-10 and the indicator shape derivative for the gradient): FP32 flops
+# (FMA = 2) and transcendentals by kind.  The sweeps share phase factors along
+# triangle strips and so execute fewer transcendentals than this count; the
+# count is the algorithm's, not the implementation's.
 ALG = {
-    "fwd": {"flops": 36.0, "trans": 7.0},
-    "vjp_volume": {"flops": 50.0, "trans": 9.0},
-    "vjp_surface": {"flops": 80.0, "trans": 9.0},
+    "fwd": {"flops": 36.0, "sin": 3, "cos": 3, "rcp": 1},
+    "vjp_volume": {"flops": 50.0, "sin": 3, "cos": 3, "rcp": 3},
+    "vjp_surface": {"flops": 80.0, "sin": 3, "cos": 3, "rcp": 3},
 }
 
 
@@ -76,9 +77,13 @@ def measured_traffic(kernel: str):
     return TRAFFIC["bytes_per_launch"]
 
 
-def flop_eq(kind: str) -> float:
+def flop_eq(kind: str, rates: dict) -> float:
+    """FP32 flop-equivalents of one pair: its flops plus each transcendental
+    priced at the measured cost of its kind, PEAK / (measured lane rate), so
+    that pairs/s x flop_eq / PEAK is the fraction of the pair rate the ALU
+    allows when flops and transcendentals share it (times add)."""
     a = ALG[kind]
-    return a["flops"] + TRANS_FLOP_EQ * a["trans"]
+    return a["flops"] + sum(a[t] * PEAK_TFLOPS * 1e12 / rates[t] for t in TRANS_KINDS)
 
 
 def cpu_baseline(case, grid, sigma, mode, seconds: float):
@@ -116,9 +121,78 @@ def cpu_baseline(case, grid, sigma, mode, seconds: float):
         n_tot, tf_tot, tv_tot = n_tot + nf, tf_tot + tf, tv_tot + tv
     pairs = n_tot * nt
     rate = pairs / (tf_tot + tv_tot)
-    return {"value": rate, "unit": "pairs/s", "cores": ref.num_threads(), "kind": "oracle",
+    cores = ref.num_threads()
+    # the same sample on one thread, for a fixed fraction of the budget
+    ref.set_num_threads(1)
+    try:
+        n1 = max(2, int(n_tot * 0.25 / max(cores, 1)))
+        t1f, t1v = run(n1)
+    finally:
+        ref.set_num_threads(cores)
+    return {"value": rate, "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_tot} of {len(xb)} band frequencies (random) x {nt} triangles, forward + gradient, "
-                      f"{tf_tot + tv_tot:.1f} s (fwd {pairs / tf_tot:.3g} pairs/s, grad {pairs / tv_tot:.3g} pairs/s)"}
+                      f"{tf_tot + tv_tot:.1f} s (fwd {pairs / tf_tot:.3g} pairs/s, grad {pairs / tv_tot:.3g} pairs/s)",
+            "one_thread": {"value": n1 * nt / (t1f + t1v), "unit": "pairs/s",
+                           "sample": f"{n1} band frequencies x {nt} triangles, {t1f + t1v:.1f} s"},
+            "cpu_model": cpu_model(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bench_sweeps(dm, h, reps: int = 10) -> dict:
+    """The paper's mesh-transform benchmark shapes (its Sec. 5 figure), on the
+    whole spectrum (band threshold 0, the exact transform), forward render
+    only: (a) the 80-triangle icosphere over images of 32^3 ... 256^3 voxels,
+    time and library memory; (b) a 100^3 image over icospheres of 320 ...
+    20480 triangles, time against the triangle count."""
+    import torch
+    from workloads import configs
+
+    def time_render(case):
+        topo = h.topology(case.F, n_verts=len(case.V))
+        V = torch.tensor(case.V, device="cuda:0")
+        dm.render(h, V, topo, case.sigma, case.grid)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(s)
+            dm.render(h, V, topo, case.sigma, case.grid)
+            b.record(s)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        n_band = float(dm.band_size(h, case.grid, case.sigma))
+        return ms, n_band, case.F.shape[0]
+
+    by_size = []
+    for n in (32, 64, 128, 256):
+        c = configs.sphere_case(sub=1, radius=0.3 * n, n=(n, n, n), tau=0.0)
+        ms, nb, nt = time_render(c)
+        by_size.append({"n": n, "n_triangles": nt, "entries": nb, "ms": ms, "pairs_per_s": nb * nt / (ms * 1e-3),
+                        "library_bytes": h.memory_in_use()})
+    by_tris = []
+    for sub in (2, 3, 4, 5):
+        c = configs.sphere_case(sub=sub, radius=30.0, n=(100, 100, 100), tau=0.0)
+        ms, nb, nt = time_render(c)
+        by_tris.append({"n_triangles": nt, "entries": nb, "ms": ms, "pairs_per_s": nb * nt / (ms * 1e-3)})
+    t = np.array([r["n_triangles"] for r in by_tris], float)
+    m = np.array([r["ms"] for r in by_tris])
+    slope, icpt = np.polyfit(t, m, 1)
+    resid = float(np.max(np.abs(m - (slope * t + icpt)) / m))
+    return {"workload": "icosphere (80 triangles) over cubic images 32^3..256^3, and a 100^3 image over "
+                        "icospheres of 320..20480 triangles; unit voxels, sigma (1, 1, 2.5), full spectrum "
+                        "(tau = 0), forward render, median of 10",
+            "by_image_size": by_size, "by_triangles": by_tris,
+            "linear_fit_ms": {"per_1k_triangles": slope * 1e3, "intercept": icpt, "max_rel_residual": resid}}
 
 
 def bench_batch(dm, h, reps: int = 2) -> dict:
@@ -265,12 +339,14 @@ def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_in
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["volume", "surface"], default="volume")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", action="store_true", help="add the 64-cell batched vs looped comparison")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="add the paper's mesh-transform benchmark shapes (image size, triangle count)")
     ap.add_argument("--fit", action="store_true",
                     help="add the staggered shape / PSF fitting steps on the single-cell workload")
     ap.add_argument("--serve", type=float, nargs="*", default=None,
@@ -302,6 +378,8 @@ def main() -> int:
     n_band = dm.band_size(h, g, sigma)
     nt = case.F.shape[0]
     pairs = float(n_band) * nt
+    from paper_2303_10440_amd import probe
+    rates = probe.alu_rates()
 
     for _ in range(args.warmup):
         dm.render_vjp(h, V, topo, sigma, g, G, want_image=True)
@@ -332,22 +410,27 @@ def main() -> int:
     vkind = "vjp_volume" if mode == configs.VOLUME else "vjp_surface"
     sweeps = {
         "fwd": {"avg_ms": fwd_ms / max(fwd_launch, 1), "pairs_per_s": fwd_pairs / (fwd_ms * 1e-3),
-                "flop_eq_per_pair": flop_eq("fwd")},
+                "flop_eq_per_pair": flop_eq("fwd", rates),
+                "frac": fwd_pairs / (fwd_ms * 1e-3) * flop_eq("fwd", rates) / (PEAK_TFLOPS * 1e12)},
         "vjp": {"avg_ms": vjp_ms / max(vjp_launch, 1), "pairs_per_s": vjp_pairs / (vjp_ms * 1e-3),
-                "flop_eq_per_pair": flop_eq(vkind)},
+                "flop_eq_per_pair": flop_eq(vkind, rates),
+                "frac": vjp_pairs / (vjp_ms * 1e-3) * flop_eq(vkind, rates) / (PEAK_TFLOPS * 1e12)},
     }
     dom = "fwd" if fwd_ms >= vjp_ms else "vjp"
     dkind = "fwd" if dom == "fwd" else vkind
     launches = fwd_launch if dom == "fwd" else vjp_launch
     dms = (fwd_ms if dom == "fwd" else vjp_ms) / max(launches, 1)
     per_launch_pairs = (fwd_pairs if dom == "fwd" else vjp_pairs) / max(launches, 1)
-    achieved = per_launch_pairs * flop_eq(dkind) / (dms * 1e-3) / 1e12
+    achieved = per_launch_pairs * flop_eq(dkind, rates) / (dms * 1e-3) / 1e12
     kname = ("k_fwd_lanes" if dom == "fwd" else "k_vjp_lanes") + ("<0>" if mode == configs.VOLUME else "<1>")
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(kname),
                 "kernel": kname,
                 "avg_launch_ms": dms, "pairs_per_launch": per_launch_pairs,
-                "flop_eq_per_pair": flop_eq(dkind)}
+                "flop_eq_per_pair": flop_eq(dkind, rates),
+                "algorithmic_per_pair": ALG[dkind],
+                "measured_lane_rates_per_s": {k: rates[k] for k in ("fma",) + TRANS_KINDS},
+                "mix_time_over_sum": rates["mix_over_sum"]}
 
     out = {
         "metric": METRIC,
@@ -382,6 +465,8 @@ def main() -> int:
         out["batched"] = bench_batch(dm, h)
     if args.fit:
         out["fit"] = bench_fit(dm, h, case, mode)
+    if args.sweeps:
+        out["sweeps_paper_shapes"] = bench_sweeps(dm, h)
     if args.serve is not None:
         out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:

@@ -337,3 +337,12 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Thread count of later parallel regions (for timing the oracle on fewer cores). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -69,6 +69,7 @@ def _c():
         L.oracle_tri_f.argtypes = [dp, dp]
         L.oracle_tri_dfdv.argtypes = [dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -87,6 +88,12 @@ def _p(a, t):
 
 def num_threads() -> int:
     return int(_c().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the OpenMP loops from now on (timing only; results do not
+    depend on it)."""
+    _c().oracle_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------- primitives

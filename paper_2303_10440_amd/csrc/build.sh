@@ -1,5 +1,6 @@
 #!/bin/bash
-# Builds libdeltamic.so for gfx950 in this directory's parent package folder.
+# Builds libdeltamic.so (and the ALU probe library libdmprobe.so) for gfx950
+# in this directory's parent package folder.
 set -euo pipefail
 HERE="$(cd "$(dirname "${BASH_SOURCE[0]}")" && pwd)"
 OUT="${1:-$HERE/../libdeltamic.so}"
@@ -14,3 +15,8 @@ trap 'rm -rf "$TMP"' EXIT
   -L"$ROCM/lib" -lrocfft -Wl,-rpath,"$ROCM/lib"
 mv -f "$OUT.tmp" "$OUT"
 echo "built $OUT"
+# ALU throughput probes used by the benchmark to price the sweeps (own library)
+PROBE="$(dirname "$OUT")/libdmprobe.so"
+"$ROCM/bin/hipcc" "${FLAGS[@]}" -shared -o "$PROBE.tmp" "$HERE/dm_probe.hip"
+mv -f "$PROBE.tmp" "$PROBE"
+echo "built $PROBE"
