@@ -54,11 +54,11 @@ ALG = {
 # hash of the kernel file differs, the benchmark reports traffic as null.
 TRAFFIC = {
     "kernel": "k_vjp_lanes<0>",
-    "source_sha256": "086ce461a18da5eb2a479bba5c0278d87255a1759d5f43ea27155f2d5ca2ca40",
-    # FETCH_SIZE 2,452,689 KiB x 2.000 (a 256 MiB copy reads 131,089 KiB) and
-    # WRITE_SIZE 14,331 KiB x 1.000 (the copy writes 262,144 KiB), per launch
-    "read_bytes": 2452689.4 * 1024 * 2.0,
-    "write_bytes": 14331.1 * 1024 * 1.0,
+    "source_sha256": "cd80cfa78d82f068d2612f485fbbeb8aa2080d49274ae980b71781137f6b31da",
+    # FETCH_SIZE 2,532,500 KiB x 2.000 (a 256 MiB copy reads 131,089 KiB) and
+    # WRITE_SIZE 55,181 KiB x 1.000 (the copy writes 262,144 KiB), per launch
+    "read_bytes": 2532500.1 * 1024 * 2.0,
+    "write_bytes": 55181.1 * 1024 * 1.0,
     "profile": "profiles/k_vjp_lanes_cfg3_volume.md",
 }
 TRAFFIC["bytes_per_launch"] = TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
@@ -148,7 +148,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def bench_sweeps(dm, h, reps: int = 10) -> dict:
+def bench_sweeps(dm, reps: int = 10) -> dict:
     """The paper's mesh-transform benchmark shapes (its Sec. 5 figure), on the
     whole spectrum (band threshold 0, the exact transform), forward render
     only: (a) the 80-triangle icosphere over images of 32^3 ... 256^3 voxels,
@@ -156,6 +156,7 @@ def bench_sweeps(dm, h, reps: int = 10) -> dict:
     20480 triangles, time against the triangle count."""
     import torch
     from workloads import configs
+    h = dm.Handle(0)
 
     def time_render(case):
         topo = h.topology(case.F, n_verts=len(case.V))
@@ -178,7 +179,7 @@ def bench_sweeps(dm, h, reps: int = 10) -> dict:
         c = configs.sphere_case(sub=1, radius=0.3 * n, n=(n, n, n), tau=0.0)
         ms, nb, nt = time_render(c)
         by_size.append({"n": n, "n_triangles": nt, "entries": nb, "ms": ms, "pairs_per_s": nb * nt / (ms * 1e-3),
-                        "library_bytes": h.memory_in_use()})
+                        "library_bytes_cumulative": h.memory_in_use()})
     by_tris = []
     for sub in (2, 3, 4, 5):
         c = configs.sphere_case(sub=sub, radius=30.0, n=(100, 100, 100), tau=0.0)
@@ -466,7 +467,7 @@ def main() -> int:
     if args.fit:
         out["fit"] = bench_fit(dm, h, case, mode)
     if args.sweeps:
-        out["sweeps_paper_shapes"] = bench_sweeps(dm, h)
+        out["sweeps_paper_shapes"] = bench_sweeps(dm)
     if args.serve is not None:
         out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:
