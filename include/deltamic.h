@@ -129,6 +129,27 @@ dm_status dm_topology_destroy(dm_topology* t);
 /* closed = 1 if closed and consistently oriented. */
 dm_status dm_topology_info(const dm_topology* t, int32_t* n_faces, int32_t* n_verts, int32_t* closed);
 
+/* Smoothed update direction of the shape step (paper Sec. 5.2): the vertex
+ * gradient filtered twice by the inverse of I + lambda L,
+ *     out = (I + lambda L)^{-2} grad,
+ * with L = D - A the combinatorial Laplacian of the mesh graph (D the vertex
+ * degrees, A the adjacency of the mesh edges; a vertex on no edge has a row
+ * of the identity).  The paper uses lambda = 50.
+ * grad, out: device [n_verts][3] float32 (row-major, the layout of
+ * dm_render_vjp's dL_dverts); out may be the same array as grad.  Each solve
+ * runs conjugate gradients (Jacobi preconditioner, float64 dot products) on
+ * the three columns together until every column's residual is at most tol
+ * times its right-hand side, or for max_iter iterations.  info (device, 4
+ * floats, optional) receives {iterations, relative residual} of the first and
+ * of the second solve; reaching max_iter is not an error, the residuals tell.
+ * The topology owns the workspace (12 n_verts floats, allocated on the first
+ * call and counted against the budget), so calls with one topology must be
+ * ordered on one stream.  Asynchronous on stream.  Errors: DM_ERR_ARG for
+ * NULL pointers, a topology of another handle, lambda negative or not
+ * finite, max_iter < 1 or tol <= 0; DM_ERR_BUDGET for the workspace. */
+dm_status dm_laplace_smooth(dm_handle* h, dm_topology* topo, float lambda, const float* grad, float* out,
+                            int32_t max_iter, float tol, float* info, void* stream);
+
 /* The triangle order a topology uses internally, computed on the host (no
  * device needed): greedy triangle strips, in which every triangle after the
  * first of a strip shares the edge formed by the previous triangle's last two

@@ -105,6 +105,7 @@ def _load():
         "dm_topology_destroy": [vp],
         "dm_topology_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "dm_topology_strips": [vp, i32, vp, vp, ctypes.POINTER(i32)],
+        "dm_laplace_smooth": [vp, vp, ctypes.c_float, vp, vp, i32, ctypes.c_float, vp, vp],
         "dm_band_size": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), ctypes.POINTER(i64), vp],
         "dm_band_export": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), vp, vp, vp, vp],
         "dm_render": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CPsf), ctypes.POINTER(CGrid), vp, vp, vp],
@@ -287,6 +288,30 @@ class Topology:
             self.close()
         except Exception:
             pass
+
+
+def laplace_smooth(h: Handle, topo: Topology, grad, lam: float = 50.0, max_iter: int = 2000, tol: float = 1e-6,
+                   out=None, with_info: bool = False):
+    """(I + lam L)^{-2} grad on the device (dm_laplace_smooth); grad is a
+    float32 [n_verts, 3] device tensor.  With with_info, also returns
+    (iterations, relative residual) of both solves."""
+    torch = _torch()
+    if not (isinstance(grad, torch.Tensor) and grad.is_cuda and grad.dtype == torch.float32):
+        raise TypeError("grad must be a float32 device tensor")
+    if tuple(grad.shape) != (topo.n_verts, 3):
+        raise ValueError(f"grad must have shape [{topo.n_verts}, 3]")
+    g = grad.contiguous()
+    if out is None:
+        out = torch.empty_like(g)
+    info = torch.zeros(4, dtype=torch.float32, device=g.device) if with_info else None
+    _check(_load().dm_laplace_smooth(h.ptr, topo.ptr, float(lam), ctypes.c_void_p(g.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), int(max_iter), float(tol),
+                                     ctypes.c_void_p(info.data_ptr() if info is not None else 0),
+                                     _stream(g.device.index or 0)), "dm_laplace_smooth")
+    if with_info:
+        i = info.cpu().tolist()
+        return out, {"iters": (int(i[0]), int(i[2])), "residual": (i[1], i[3])}
+    return out
 
 
 def _mesh(verts, topo: Topology) -> CMesh:

@@ -137,7 +137,11 @@ struct dm_topology {
   int32_t* csr_off = nullptr;   // device [nv+1]
   int32_t* csr_ent = nullptr;   // device [3 nt] = 3 t + p (strip-order t, p)
   int32_t* flags = nullptr;     // device [nt]: TRI_STRIP_START, TRI_REVERSED
+  int32_t* adj_off = nullptr;   // device [nv+1]: vertex adjacency (mesh edges), CSR
+  int32_t* adj_nbr = nullptr;   // device [2 n_edges]
   size_t bytes = 0;
+  float* smooth_ws = nullptr;   // device workspace of dm_laplace_smooth (allocated on first use)
+  size_t smooth_bytes = 0;
 };
 
 namespace {
@@ -1003,6 +1007,23 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
   for (int v = 0; v < n_verts; ++v) off[v + 1] += off[v];
   std::vector<int32_t> fill(off.begin(), off.end() - 1);
   for (size_t i = 0; i < F.size(); ++i) ent[fill[F[i]]++] = (int32_t)i;   // i = 3 t + p
+  // vertex adjacency: both directions of every undirected mesh edge, unique
+  std::vector<uint64_t> und;
+  und.reserve(2 * e.size());
+  for (uint64_t x : e) {
+    const uint64_t a = x >> 32, b = x & 0xffffffffu;
+    if (a == b) continue;
+    und.push_back((a << 32) | b);
+    und.push_back((b << 32) | a);
+  }
+  std::sort(und.begin(), und.end());
+  und.erase(std::unique(und.begin(), und.end()), und.end());
+  std::vector<int32_t> aoff((size_t)n_verts + 1, 0), anbr(und.size());
+  for (size_t i = 0; i < und.size(); ++i) {
+    aoff[(size_t)(und[i] >> 32) + 1]++;
+    anbr[i] = (int32_t)(und[i] & 0xffffffffu);
+  }
+  for (int v = 0; v < n_verts; ++v) aoff[v + 1] += aoff[v];
   auto t = std::make_unique<dm_topology>();
   t->h = h;
   t->nt = n_faces;
@@ -1010,19 +1031,24 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
   t->closed = closed ? 1 : 0;
   t->n_strips = n_strips;
   const size_t bf = align_up(F.size() * 4), bo = align_up(off.size() * 4), be = align_up(ent.size() * 4),
-               bl = align_up(fl.size() * 4);
+               bl = align_up(fl.size() * 4), bao = align_up(aoff.size() * 4), ban = align_up(anbr.size() * 4);
   void* mem = nullptr;
-  DM_TRY(dev_alloc(h, &mem, bf + bo + be + bl));
-  t->bytes = bf + bo + be + bl;
+  DM_TRY(dev_alloc(h, &mem, bf + bo + be + bl + bao + ban));
+  t->bytes = bf + bo + be + bl + bao + ban;
   t->faces = static_cast<int32_t*>(mem);
   t->csr_off = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf);
   t->csr_ent = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo);
   t->flags = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be);
+  t->adj_off = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl);
+  t->adj_nbr = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl + bao);
   hipError_t err = hipSuccess;
   if (!F.empty()) err = hipMemcpy(t->faces, F.data(), F.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemcpy(t->csr_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess && !ent.empty()) err = hipMemcpy(t->csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess && !fl.empty()) err = hipMemcpy(t->flags, fl.data(), fl.size() * 4, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(t->adj_off, aoff.data(), aoff.size() * 4, hipMemcpyHostToDevice);
+  if (err == hipSuccess && !anbr.empty())
+    err = hipMemcpy(t->adj_nbr, anbr.data(), anbr.size() * 4, hipMemcpyHostToDevice);
   if (err != hipSuccess) {
     dev_free(h, mem, t->bytes);
     return fail(DM_ERR_DEVICE, "topology upload: %s", hipGetErrorString(err));
@@ -1054,8 +1080,32 @@ dm_status dm_topology_destroy(dm_topology* t) {
   DeviceGuard dg(t->h->device);
   (void)hipDeviceSynchronize();
   dev_free(t->h, t->faces, t->bytes);
+  dev_free(t->h, t->smooth_ws, t->smooth_bytes);
   t->h->topo_count--;
   delete t;
+  return DM_OK;
+}
+
+dm_status dm_laplace_smooth(dm_handle* h, dm_topology* t, float lambda, const float* grad, float* out,
+                            int32_t max_iter, float tol, float* info, void* stream) {
+  g_err.clear();
+  if (!h || !t || !grad || !out) return fail(DM_ERR_ARG, "NULL argument");
+  if (t->h != h) return fail(DM_ERR_ARG, "topology belongs to another handle");
+  if (!(lambda >= 0.0f) || !std::isfinite(lambda)) return fail(DM_ERR_ARG, "lambda must be finite and >= 0");
+  if (max_iter < 1) return fail(DM_ERR_ARG, "max_iter must be at least 1");
+  if (!(tol > 0.0f)) return fail(DM_ERR_ARG, "tol must be > 0");
+  if (t->nv == 0) return DM_OK;
+  DeviceGuard dg(h->device);
+  const size_t need = laplace_smooth_workspace(t->nv);
+  if (t->smooth_bytes < need) {
+    void* mem = nullptr;
+    DM_TRY(dev_alloc(h, &mem, need));
+    dev_free(h, t->smooth_ws, t->smooth_bytes);
+    t->smooth_ws = static_cast<float*>(mem);
+    t->smooth_bytes = need;
+  }
+  HIP_TRY(launch_laplace_smooth(t->nv, t->adj_off, t->adj_nbr, lambda, grad, out, t->smooth_ws, max_iter, tol, info,
+                                static_cast<hipStream_t>(stream)));
   return DM_OK;
 }
 

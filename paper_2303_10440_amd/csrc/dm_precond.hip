@@ -1,0 +1,187 @@
+// gfx950 kernel of the smoothed vertex update of the shape step.
+//
+// The paper's shape optimisation (Sec. 5.2) moves the vertices along the
+// loss gradient filtered by (I + lambda L)^{-2}, L the Laplacian of the mesh
+// graph, which spreads each vertex's gradient over its neighbourhood and
+// lets large steps keep the mesh regular.  Here L = D - A is the
+// combinatorial graph Laplacian (D the vertex degrees, A the adjacency of the
+// mesh edges) and the two solves with I + lambda L (symmetric positive
+// definite for lambda >= 0) are done by conjugate gradients with the Jacobi
+// preconditioner diag(I + lambda L) = 1 + lambda deg.
+//
+// One workgroup solves the three systems of a gradient (its x, y and z
+// components, vertex-major [n_v][3] like the gradient itself) at once: the
+// mesh is small (10^3 - 10^5 vertices), the iteration count is what costs,
+// and a single workgroup synchronises with barriers instead of kernel
+// launches.  Dot products are accumulated in float64 and reduced in a fixed
+// order, so results are bitwise reproducible.  The loop ends once every
+// component's residual is below tol times its right-hand side, or after
+// max_iter iterations.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dm_internal.h"
+
+namespace dm {
+namespace {
+
+constexpr int CG_T = 1024;
+constexpr int CG_W = CG_T / 64;
+
+struct CgLds {
+  double part[CG_W][3];
+  double tot[3];
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Sum of v[0..2] over the workgroup (fixed order), returned to every thread.
+__device__ void block_sum3(double v[3], CgLds& L) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double s = wave_sum_d(v[c]);
+    if (lane == 0) L.part[w][c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+    for (int i = 0; i < CG_W; ++i) s += L.part[i][threadIdx.x];
+    L.tot[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = L.tot[c];
+  __syncthreads();
+}
+
+// (I + lam L) x = b by Jacobi-preconditioned CG; b, x, r, p, q are [nv][3].
+// b is read only before x is first written, so x may be the array b.
+// Returns the iterations used and writes the worst relative residual of the
+// three components to *res.
+__device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr, float lam,
+                        const float* b, float* x, float* __restrict__ r, float* __restrict__ p,
+                        float* __restrict__ q, int max_iter, float tol, float* res, CgLds& L) {
+  double bb[3] = {0.0, 0.0, 0.0}, rz[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nv; i += CG_T) {
+    const float dinv = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float bi = b[3 * i + c];
+      r[3 * i + c] = bi;
+      p[3 * i + c] = bi * dinv;
+      bb[c] += (double)bi * bi;
+      rz[c] += (double)bi * (bi * dinv);
+    }
+  }
+  // x = 0 after the reads of b above (x may be the same array as b)
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += CG_T)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[3 * i + c] = 0.0f;
+  block_sum3(bb, L);
+  block_sum3(rz, L);
+  double rr[3] = {bb[0], bb[1], bb[2]};
+  const double tol2 = (double)tol * tol;
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    if (rr[0] <= tol2 * bb[0] && rr[1] <= tol2 * bb[1] && rr[2] <= tol2 * bb[2]) break;
+    // q = (I + lam L) p, and p.q
+    double pq[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nv; i += CG_T) {
+      const int o0 = off[i], o1 = off[i + 1];
+      float s[3] = {0.0f, 0.0f, 0.0f};
+      for (int o = o0; o < o1; ++o) {
+        const int j = nbr[o];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += p[3 * j + c];
+      }
+      const float d = fmaf(lam, (float)(o1 - o0), 1.0f);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float pi = p[3 * i + c];
+        const float qi = fmaf(d, pi, -lam * s[c]);
+        q[3 * i + c] = qi;
+        pq[c] += (double)pi * qi;
+      }
+    }
+    block_sum3(pq, L);
+    float alpha[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) alpha[c] = pq[c] > 0.0 ? (float)(rz[c] / pq[c]) : 0.0f;
+    // x += alpha p, r -= alpha q; r.r and r.z with z = r / d
+    double rn[3] = {0.0, 0.0, 0.0}, rzn[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nv; i += CG_T) {
+      const float dinv = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x[3 * i + c] = fmaf(alpha[c], p[3 * i + c], x[3 * i + c]);
+        const float ri = fmaf(-alpha[c], q[3 * i + c], r[3 * i + c]);
+        r[3 * i + c] = ri;
+        rn[c] += (double)ri * ri;
+        rzn[c] += (double)ri * (ri * dinv);
+      }
+    }
+    block_sum3(rn, L);
+    block_sum3(rzn, L);
+    float beta[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      beta[c] = rz[c] > 0.0 ? (float)(rzn[c] / rz[c]) : 0.0f;
+      rz[c] = rzn[c];
+      rr[c] = rn[c];
+    }
+    // p = z + beta p
+    for (int i = threadIdx.x; i < nv; i += CG_T) {
+      const float dinv = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[3 * i + c] = fmaf(beta[c], p[3 * i + c], r[3 * i + c] * dinv);
+    }
+    __syncthreads();
+  }
+  double worst = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (bb[c] > 0.0) worst = fmax(worst, sqrt(rr[c] / bb[c]));
+  *res = (float)worst;
+  return it;
+}
+
+__global__ void __launch_bounds__(CG_T) k_laplace_smooth(int nv, const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ nbr, float lam,
+                                                          const float* g, float* out, float* __restrict__ ws,
+                                                          int max_iter, float tol, float* __restrict__ info) {
+  __shared__ CgLds L;
+  const size_t n3 = (size_t)3 * nv;
+  float* y = ws;
+  float* r = ws + n3;
+  float* p = ws + 2 * n3;
+  float* q = ws + 3 * n3;
+  float res1 = 0.0f, res2 = 0.0f;
+  const int it1 = cg_solve(nv, off, nbr, lam, g, y, r, p, q, max_iter, tol, &res1, L);
+  __syncthreads();
+  const int it2 = cg_solve(nv, off, nbr, lam, y, out, r, p, q, max_iter, tol, &res2, L);
+  if (info != nullptr && threadIdx.x == 0) {
+    info[0] = (float)it1;
+    info[1] = res1;
+    info[2] = (float)it2;
+    info[3] = res2;
+  }
+}
+
+}  // namespace
+
+size_t laplace_smooth_workspace(int nv) { return sizeof(float) * 12 * (size_t)nv; }
+
+hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, float lam, const float* g,
+                                 float* out, float* ws, int max_iter, float tol, float* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_laplace_smooth, dim3(1), dim3(CG_T), 0, s, nv, adj_off, adj_nbr, lam, g, out, ws, max_iter,
+                     tol, info);
+  return hipGetLastError();
+}
+
+}  // namespace dm

@@ -18,8 +18,11 @@ configurations, Sigma = diag(sigma_xy^2, sigma_xy^2, sigma_z^2), so
 dL/dsigma_xy = 2 sigma_xy (dL/dSigma_xx + dL/dSigma_yy) and
 dL/dsigma_z = 2 sigma_z dL/dSigma_zz.
 
-The paper's vertex update (AdamUniform with Laplacian preconditioning) is not
-built; shape steps use Adam (or plain gradient steps) on the vertex array.
+Vertex updates: Adam, the paper's uniform Adam (one second-moment scale for
+the whole vertex array, its maximum, so every vertex moves by a step of the
+same size), or plain gradient steps; optionally on the smoothed gradient
+(I + lambda L)^{-2} dL/dV of Sec. 5.2 (``dm.laplace_smooth``, lambda = 50 in
+the paper).
 """
 from __future__ import annotations
 
@@ -64,6 +67,19 @@ class _Adam:
         x.sub_(self.lr * mh / (vh.sqrt() + self.eps))
 
 
+class _AdamUniform(_Adam):
+    """Adam whose second-moment estimate is replaced by its maximum over the
+    array: the update direction is m_hat / sqrt(max v_hat)."""
+
+    def step(self, x, g):
+        self.t += 1
+        self.m.mul_(self.b1).add_(g, alpha=1.0 - self.b1)
+        self.v.mul_(self.b2).addcmul_(g, g, value=1.0 - self.b2)
+        mh = self.m / (1.0 - self.b1 ** self.t)
+        vmax = self.v.max() / (1.0 - self.b2 ** self.t)
+        x.sub_(self.lr * mh / (vmax.sqrt() + self.eps))
+
+
 class _Sgd:
     def __init__(self, like, lr: float):
         self.lr = lr
@@ -78,8 +94,10 @@ class FitConfig:
     lr_psf: float = 0.02
     shape_steps: int = 10            # per round
     psf_steps: int = 2               # per round
-    optimizer: str = "adam"          # "adam" or "sgd"
+    optimizer: str = "adam"          # "adam", "adam_uniform" or "sgd" (vertex steps; PSF steps use Adam or sgd)
     weighted: bool = True            # weighted L2 for the shape steps (plain L2 if False)
+    smooth_lambda: float | None = None   # filter dL/dV by (I + lambda L)^{-2} before the vertex step
+    smooth_tol: float = 1e-6
 
 
 class StaggeredFit:
@@ -97,9 +115,9 @@ class StaggeredFit:
         self.verts = verts
         self.psf = torch.tensor([sigma_xy, sigma_z], dtype=torch.float64)
         self.grid_exact = dataclasses.replace(grid, tau=0.0)
-        opt = _Adam if self.cfg.optimizer == "adam" else _Sgd
-        self.opt_v = opt(verts, self.cfg.lr_shape)
-        self.opt_p = opt(self.psf, self.cfg.lr_psf)
+        opt_v = {"adam": _Adam, "adam_uniform": _AdamUniform, "sgd": _Sgd}[self.cfg.optimizer]
+        self.opt_v = opt_v(verts, self.cfg.lr_shape)
+        self.opt_p = (_Sgd if self.cfg.optimizer == "sgd" else _Adam)(self.psf, self.cfg.lr_psf)
         self.history: list[tuple[str, float]] = []
 
     def sigma6(self):
@@ -131,6 +149,9 @@ class StaggeredFit:
 
     def shape_step(self) -> float:
         loss, dv = self.shape_gradient()
+        if self.cfg.smooth_lambda is not None:
+            dv = dm.laplace_smooth(self.h, self.topo, dv.contiguous(), lam=self.cfg.smooth_lambda,
+                                   tol=self.cfg.smooth_tol)
         self.opt_v.step(self.verts, dv)
         self.history.append(("shape", loss))
         return loss

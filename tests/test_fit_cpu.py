@@ -45,3 +45,13 @@ def test_adam_matches_torch_adam():
 def test_sigma6_and_psf_chain_rule():
     s = fit.sigma6(1.5, 3.0)
     assert s == (2.25, 2.25, 9.0, 0.0, 0.0, 0.0)
+
+
+def test_adam_uniform_moves_every_entry_by_the_same_scale():
+    rng = np.random.default_rng(6)
+    x = torch.zeros((9, 3), dtype=torch.float64)
+    g = torch.tensor(rng.standard_normal((9, 3)), dtype=torch.float64)
+    opt = fit._AdamUniform(x, lr=0.1, eps=0.0)
+    opt.step(x, g)
+    # first step: m_hat = g, v_hat = g^2, so the step is lr g / max|g|
+    assert torch.allclose(x, -0.1 * g / g.abs().max(), rtol=0, atol=1e-15)
