@@ -263,6 +263,18 @@ def bench_fit(dm, h, case, mode, shape_steps: int = 10, psf_steps: int = 4) -> d
         F.psf_step()
     e2.record(s)
     torch.cuda.synchronize()
+    # the paper's vertex update: uniform Adam on the Laplacian-filtered gradient
+    Vs = torch.tensor((c + 0.97 * (case.V - c)).astype(np.float32), device=dev)
+    Fs = fit.StaggeredFit(h, topo, Vs, s_xy, s_z, g, target,
+                          fit.FitConfig(lr_shape=0.005, optimizer="adam_uniform", smooth_lambda=50.0))
+    Fs.shape_step()
+    torch.cuda.synchronize()
+    e3, e4 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e3.record(s)
+    for _ in range(shape_steps):
+        Fs.shape_step()
+    e4.record(s)
+    torch.cuda.synchronize()
     n_band = float(dm.band_size(h, g, case.sigma))
     n_full = float(dm.band_size(h, dataclasses.replace(g, tau=0.0), case.sigma))
     ts, tp = e0.elapsed_time(e1) / shape_steps, e1.elapsed_time(e2) / psf_steps
@@ -270,11 +282,50 @@ def bench_fit(dm, h, case, mode, shape_steps: int = 10, psf_steps: int = 4) -> d
     return {"workload": "single-cell fit: shape steps on the band OTF > 1e-3, PSF steps on the full "
                         "spectrum (tau = 0), start 3% shrunk and PSF 20% wide",
             "shape_step_ms": ts, "psf_step_ms": tp,
+            "shape_step_smoothed_uniform_adam_ms": e3.elapsed_time(e4) / shape_steps,
             "shape_pairs_per_s": n_band * case.F.shape[0] / (ts * 1e-3),
             "psf_pairs_per_s": n_full * case.F.shape[0] / (tp * 1e-3),
             "band_entries": n_band, "full_spectrum_entries": n_full,
             "first_shape_loss": losses[0], "last_shape_loss": [l for k, l in F.history if k == "shape"][-1],
             "psf": [float(x) for x in F.psf]}
+
+
+def bench_smooth(dm, reps: int = 20) -> dict:
+    """The shape step's Laplacian filter (I + 50 L)^{-2} g (dm_laplace_smooth)
+    on the single-cell mesh (2562 vertices) and a 20252-vertex geodesic
+    sphere, random gradient, relative residual 1e-6 per solve; the FP64
+    oracle (two sparse direct solves per column, scipy) timed beside it."""
+    import torch
+    from oracle import smoothing as S
+    from workloads import configs, meshes
+    h = dm.Handle(0)
+    out = []
+    c3 = configs.cfg3()
+    Vg, Fg = meshes.geodesic_sphere(45)
+    for name, F, nv in (("cfg3 cell", c3.F, len(c3.V)), ("geodesic-45 sphere", Fg, len(Vg))):
+        topo = h.topology(F, n_verts=nv)
+        g = torch.tensor(np.random.default_rng(0).standard_normal((nv, 3)).astype(np.float32), device="cuda:0")
+        o, info = dm.laplace_smooth(h, topo, g, lam=50.0, tol=1e-6, with_info=True)
+        torch.cuda.synchronize()
+        s_ = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s_)
+        for _ in range(reps):
+            dm.laplace_smooth(h, topo, g, lam=50.0, tol=1e-6, out=o)
+        e1.record(s_)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gd = g.cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        want = S.laplace_smooth(F, nv, gd, 50.0)
+        t_cpu = time.perf_counter() - t0
+        err = float(np.linalg.norm(o.cpu().numpy() - want) / np.linalg.norm(want))
+        its = info["iters"][0] + info["iters"][1]
+        out.append({"mesh": name, "n_verts": nv, "ms": ms, "cg_iterations": list(info["iters"]),
+                    "us_per_iteration": ms * 1e3 / max(its, 1), "rel_err_vs_oracle": err,
+                    "oracle_ms": t_cpu * 1e3})
+    return {"workload": "(I + 50 L)^{-2} g, L the edge-graph Laplacian, random g, CG to relative residual 1e-6 "
+                        "per solve (one workgroup, Jacobi preconditioner)", "cases": out}
 
 
 def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_inflight: int, pool: int = 32,
@@ -348,6 +399,8 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true", help="add the 64-cell batched vs looped comparison")
     ap.add_argument("--sweeps", action="store_true",
                     help="add the paper's mesh-transform benchmark shapes (image size, triangle count)")
+    ap.add_argument("--smooth", action="store_true",
+                    help="add the shape step's Laplacian filter on the cell and a 20k-vertex sphere")
     ap.add_argument("--fit", action="store_true",
                     help="add the staggered shape / PSF fitting steps on the single-cell workload")
     ap.add_argument("--serve", type=float, nargs="*", default=None,
@@ -468,6 +521,8 @@ def main() -> int:
         out["fit"] = bench_fit(dm, h, case, mode)
     if args.sweeps:
         out["sweeps_paper_shapes"] = bench_sweeps(dm)
+    if args.smooth:
+        out["smooth"] = bench_smooth(dm)
     if args.serve is not None:
         out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:

@@ -142,7 +142,7 @@ dm_status dm_topology_info(const dm_topology* t, int32_t* n_faces, int32_t* n_ve
  * times its right-hand side, or for max_iter iterations.  info (device, 4
  * floats, optional) receives {iterations, relative residual} of the first and
  * of the second solve; reaching max_iter is not an error, the residuals tell.
- * The topology owns the workspace (12 n_verts floats, allocated on the first
+ * The topology owns the workspace (13 n_verts floats, allocated on the first
  * call and counted against the budget), so calls with one topology must be
  * ordered on one stream.  Asynchronous on stream.  Errors: DM_ERR_ARG for
  * NULL pointers, a topology of another handle, lambda negative or not

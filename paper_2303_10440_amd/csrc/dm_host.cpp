@@ -139,6 +139,7 @@ struct dm_topology {
   int32_t* flags = nullptr;     // device [nt]: TRI_STRIP_START, TRI_REVERSED
   int32_t* adj_off = nullptr;   // device [nv+1]: vertex adjacency (mesh edges), CSR
   int32_t* adj_nbr = nullptr;   // device [2 n_edges]
+  int32_t* adj_tab = nullptr;   // device [nv][LAP_TABLE_W], -1 padded; nullptr if a degree exceeds the width
   size_t bytes = 0;
   float* smooth_ws = nullptr;   // device workspace of dm_laplace_smooth (allocated on first use)
   size_t smooth_bytes = 0;
@@ -1024,6 +1025,14 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
     anbr[i] = (int32_t)(und[i] & 0xffffffffu);
   }
   for (int v = 0; v < n_verts; ++v) aoff[v + 1] += aoff[v];
+  int max_deg = 0;
+  for (int v = 0; v < n_verts; ++v) max_deg = std::max(max_deg, aoff[v + 1] - aoff[v]);
+  std::vector<int32_t> atab;
+  if (max_deg <= LAP_TABLE_W) {
+    atab.assign((size_t)n_verts * LAP_TABLE_W, -1);
+    for (int v = 0; v < n_verts; ++v)
+      for (int o = aoff[v]; o < aoff[v + 1]; ++o) atab[(size_t)v * LAP_TABLE_W + (o - aoff[v])] = anbr[o];
+  }
   auto t = std::make_unique<dm_topology>();
   t->h = h;
   t->nt = n_faces;
@@ -1031,16 +1040,19 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
   t->closed = closed ? 1 : 0;
   t->n_strips = n_strips;
   const size_t bf = align_up(F.size() * 4), bo = align_up(off.size() * 4), be = align_up(ent.size() * 4),
-               bl = align_up(fl.size() * 4), bao = align_up(aoff.size() * 4), ban = align_up(anbr.size() * 4);
+               bl = align_up(fl.size() * 4), bao = align_up(aoff.size() * 4), ban = align_up(anbr.size() * 4),
+               bat = align_up(atab.size() * 4);
   void* mem = nullptr;
-  DM_TRY(dev_alloc(h, &mem, bf + bo + be + bl + bao + ban));
-  t->bytes = bf + bo + be + bl + bao + ban;
+  DM_TRY(dev_alloc(h, &mem, bf + bo + be + bl + bao + ban + bat));
+  t->bytes = bf + bo + be + bl + bao + ban + bat;
   t->faces = static_cast<int32_t*>(mem);
   t->csr_off = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf);
   t->csr_ent = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo);
   t->flags = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be);
   t->adj_off = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl);
   t->adj_nbr = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl + bao);
+  t->adj_tab = atab.empty() ? nullptr
+                            : reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl + bao + ban);
   hipError_t err = hipSuccess;
   if (!F.empty()) err = hipMemcpy(t->faces, F.data(), F.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemcpy(t->csr_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
@@ -1049,6 +1061,8 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
   if (err == hipSuccess) err = hipMemcpy(t->adj_off, aoff.data(), aoff.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess && !anbr.empty())
     err = hipMemcpy(t->adj_nbr, anbr.data(), anbr.size() * 4, hipMemcpyHostToDevice);
+  if (err == hipSuccess && !atab.empty())
+    err = hipMemcpy(t->adj_tab, atab.data(), atab.size() * 4, hipMemcpyHostToDevice);
   if (err != hipSuccess) {
     dev_free(h, mem, t->bytes);
     return fail(DM_ERR_DEVICE, "topology upload: %s", hipGetErrorString(err));
@@ -1104,8 +1118,8 @@ dm_status dm_laplace_smooth(dm_handle* h, dm_topology* t, float lambda, const fl
     t->smooth_ws = static_cast<float*>(mem);
     t->smooth_bytes = need;
   }
-  HIP_TRY(launch_laplace_smooth(t->nv, t->adj_off, t->adj_nbr, lambda, grad, out, t->smooth_ws, max_iter, tol, info,
-                                static_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_laplace_smooth(t->nv, t->adj_off, t->adj_nbr, t->adj_tab, lambda, grad, out, t->smooth_ws, max_iter,
+                                tol, info, static_cast<hipStream_t>(stream)));
   return DM_OK;
 }
 

@@ -145,11 +145,15 @@ hipError_t launch_points_finalize(int mode, const GridC& g, const float4* kf, in
 inline int nchannels(int mode) { return mode == 0 ? 3 : 10; }
 
 // Smoothed gradient (I + lam L)^{-2} g of the shape step (dm_precond.hip):
-// one workgroup, CG on the vertex adjacency CSR; ws holds
-// laplace_smooth_workspace(nv) bytes; info (device, optional) receives
-// {iterations, relative residual} of each of the two solves.
+// one workgroup, CG on the vertex adjacency (CSR, and when every degree is at
+// most LAP_TABLE_W also a table [nv][LAP_TABLE_W] of neighbours padded with
+// -1, else adj_tab = nullptr); ws holds laplace_smooth_workspace(nv) bytes;
+// info (device, optional) receives {iterations, relative residual} of each
+// of the two solves.
+constexpr int LAP_TABLE_W = 8;
 size_t laplace_smooth_workspace(int nv);
-hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, float lam, const float* g,
-                                 float* out, float* ws, int max_iter, float tol, float* info, hipStream_t s);
+hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, const int32_t* adj_tab,
+                                 float lam, const float* g, float* out, float* ws, int max_iter, float tol,
+                                 float* info, hipStream_t s);
 
 }  // namespace dm

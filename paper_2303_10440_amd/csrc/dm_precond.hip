@@ -26,36 +26,54 @@ namespace dm {
 namespace {
 
 constexpr int CG_T = 1024;
+constexpr int ADJ_W = LAP_TABLE_W;
 constexpr int CG_W = CG_T / 64;
 
 struct CgLds {
-  double part[CG_W][3];
-  double tot[3];
+  double part[CG_W][6];
+  double tot[6];
 };
 
+// One DPP lane move of a double (both halves with the same control); lanes
+// the move does not write read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes in a fixed order (within quads, half rows, rows, then
+// row pairs); the total ends in lane 63.
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  v += dpp_d<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_d<0x140, 0xF>(v);   // row_mirror
+  v += dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
   return v;
 }
 
-// Sum of v[0..2] over the workgroup (fixed order), returned to every thread.
-__device__ void block_sum3(double v[3], CgLds& L) {
+// Sum of v[0..N-1] over the workgroup (fixed order), returned to every thread.
+template <int N>
+__device__ void block_sum(double (&v)[N], CgLds& L) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < N; ++c) {
     const double s = wave_sum_d(v[c]);
-    if (lane == 0) L.part[w][c] = s;
+    if (lane == 63) L.part[w][c] = s;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < N) {
     double s = 0.0;
     for (int i = 0; i < CG_W; ++i) s += L.part[i][threadIdx.x];
     L.tot[threadIdx.x] = s;
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 3; ++c) v[c] = L.tot[c];
+  for (int c = 0; c < N; ++c) v[c] = L.tot[c];
   __syncthreads();
 }
 
@@ -63,19 +81,53 @@ __device__ void block_sum3(double v[3], CgLds& L) {
 // b is read only before x is first written, so x may be the array b.
 // Returns the iterations used and writes the worst relative residual of the
 // three components to *res.
-__device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr, float lam,
-                        const float* b, float* x, float* __restrict__ r, float* __restrict__ p,
-                        float* __restrict__ q, int max_iter, float tol, float* res, CgLds& L) {
-  double bb[3] = {0.0, 0.0, 0.0}, rz[3] = {0.0, 0.0, 0.0};
+// q_i = (I + lam L) p at vertex i: from the fixed-width neighbour table
+// (TABLE, every degree <= ADJ_W, unused slots -1: the neighbour loads do not
+// depend on each other) or from the CSR lists.
+template <bool TABLE>
+__device__ __forceinline__ void lap_row(int i, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                                        const int32_t* __restrict__ tab, const float* __restrict__ p, float s[3],
+                                        int& deg) {
+  s[0] = s[1] = s[2] = 0.0f;
+  if (TABLE) {
+    const int4 a = reinterpret_cast<const int4*>(tab)[2 * i], b = reinterpret_cast<const int4*>(tab)[2 * i + 1];
+    const int nb[ADJ_W] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    deg = 0;
+#pragma unroll
+    for (int k = 0; k < ADJ_W; ++k) {
+      if (nb[k] >= 0) {
+        ++deg;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += p[3 * nb[k] + c];
+      }
+    }
+  } else {
+    const int o0 = off[i], o1 = off[i + 1];
+    deg = o1 - o0;
+    for (int o = o0; o < o1; ++o) {
+      const int j = nbr[o];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s[c] += p[3 * j + c];
+    }
+  }
+}
+
+template <bool TABLE>
+__device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                        const int32_t* __restrict__ tab, const float* __restrict__ dinv_v, float lam, const float* b,
+                        float* x,
+                        float* __restrict__ r, float* __restrict__ p, float* __restrict__ q, int max_iter, float tol,
+                        float* res, CgLds& L) {
+  double bz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // b.b, then r.z, per component
   for (int i = threadIdx.x; i < nv; i += CG_T) {
-    const float dinv = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
+    const float dinv = dinv_v[i];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float bi = b[3 * i + c];
       r[3 * i + c] = bi;
       p[3 * i + c] = bi * dinv;
-      bb[c] += (double)bi * bi;
-      rz[c] += (double)bi * (bi * dinv);
+      bz[c] += (double)bi * bi;
+      bz[3 + c] += (double)bi * (bi * dinv);
     }
   }
   // x = 0 after the reads of b above (x may be the same array as b)
@@ -83,8 +135,9 @@ __device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* 
   for (int i = threadIdx.x; i < nv; i += CG_T)
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[3 * i + c] = 0.0f;
-  block_sum3(bb, L);
-  block_sum3(rz, L);
+  block_sum<6>(bz, L);
+  const double bb[3] = {bz[0], bz[1], bz[2]};
+  double rz[3] = {bz[3], bz[4], bz[5]};
   double rr[3] = {bb[0], bb[1], bb[2]};
   const double tol2 = (double)tol * tol;
   int it = 0;
@@ -92,15 +145,12 @@ __device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* 
     if (rr[0] <= tol2 * bb[0] && rr[1] <= tol2 * bb[1] && rr[2] <= tol2 * bb[2]) break;
     // q = (I + lam L) p, and p.q
     double pq[3] = {0.0, 0.0, 0.0};
+#pragma unroll 2
     for (int i = threadIdx.x; i < nv; i += CG_T) {
-      const int o0 = off[i], o1 = off[i + 1];
-      float s[3] = {0.0f, 0.0f, 0.0f};
-      for (int o = o0; o < o1; ++o) {
-        const int j = nbr[o];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) s[c] += p[3 * j + c];
-      }
-      const float d = fmaf(lam, (float)(o1 - o0), 1.0f);
+      float s[3];
+      int deg;
+      lap_row<TABLE>(i, off, nbr, tab, p, s, deg);
+      const float d = fmaf(lam, (float)deg, 1.0f);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float pi = p[3 * i + c];
@@ -109,35 +159,34 @@ __device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* 
         pq[c] += (double)pi * qi;
       }
     }
-    block_sum3(pq, L);
+    block_sum<3>(pq, L);
     float alpha[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) alpha[c] = pq[c] > 0.0 ? (float)(rz[c] / pq[c]) : 0.0f;
     // x += alpha p, r -= alpha q; r.r and r.z with z = r / d
-    double rn[3] = {0.0, 0.0, 0.0}, rzn[3] = {0.0, 0.0, 0.0};
+    double rn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // r.r, then r.z
     for (int i = threadIdx.x; i < nv; i += CG_T) {
-      const float dinv = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
+      const float dinv = dinv_v[i];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         x[3 * i + c] = fmaf(alpha[c], p[3 * i + c], x[3 * i + c]);
         const float ri = fmaf(-alpha[c], q[3 * i + c], r[3 * i + c]);
         r[3 * i + c] = ri;
         rn[c] += (double)ri * ri;
-        rzn[c] += (double)ri * (ri * dinv);
+        rn[3 + c] += (double)ri * (ri * dinv);
       }
     }
-    block_sum3(rn, L);
-    block_sum3(rzn, L);
+    block_sum<6>(rn, L);
     float beta[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      beta[c] = rz[c] > 0.0 ? (float)(rzn[c] / rz[c]) : 0.0f;
-      rz[c] = rzn[c];
+      beta[c] = rz[c] > 0.0 ? (float)(rn[3 + c] / rz[c]) : 0.0f;
+      rz[c] = rn[3 + c];
       rr[c] = rn[c];
     }
     // p = z + beta p
     for (int i = threadIdx.x; i < nv; i += CG_T) {
-      const float dinv = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
+      const float dinv = dinv_v[i];
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[3 * i + c] = fmaf(beta[c], p[3 * i + c], r[3 * i + c] * dinv);
     }
@@ -151,8 +200,10 @@ __device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* 
   return it;
 }
 
+template <bool TABLE>
 __global__ void __launch_bounds__(CG_T) k_laplace_smooth(int nv, const int32_t* __restrict__ off,
-                                                          const int32_t* __restrict__ nbr, float lam,
+                                                          const int32_t* __restrict__ nbr,
+                                                          const int32_t* __restrict__ tab, float lam,
                                                           const float* g, float* out, float* __restrict__ ws,
                                                           int max_iter, float tol, float* __restrict__ info) {
   __shared__ CgLds L;
@@ -161,10 +212,13 @@ __global__ void __launch_bounds__(CG_T) k_laplace_smooth(int nv, const int32_t* 
   float* r = ws + n3;
   float* p = ws + 2 * n3;
   float* q = ws + 3 * n3;
-  float res1 = 0.0f, res2 = 0.0f;
-  const int it1 = cg_solve(nv, off, nbr, lam, g, y, r, p, q, max_iter, tol, &res1, L);
+  float* dinv = ws + 4 * n3;   // 1 / diag(I + lam L)
+  for (int i = threadIdx.x; i < nv; i += CG_T) dinv[i] = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
   __syncthreads();
-  const int it2 = cg_solve(nv, off, nbr, lam, y, out, r, p, q, max_iter, tol, &res2, L);
+  float res1 = 0.0f, res2 = 0.0f;
+  const int it1 = cg_solve<TABLE>(nv, off, nbr, tab, dinv, lam, g, y, r, p, q, max_iter, tol, &res1, L);
+  __syncthreads();
+  const int it2 = cg_solve<TABLE>(nv, off, nbr, tab, dinv, lam, y, out, r, p, q, max_iter, tol, &res2, L);
   if (info != nullptr && threadIdx.x == 0) {
     info[0] = (float)it1;
     info[1] = res1;
@@ -175,12 +229,17 @@ __global__ void __launch_bounds__(CG_T) k_laplace_smooth(int nv, const int32_t* 
 
 }  // namespace
 
-size_t laplace_smooth_workspace(int nv) { return sizeof(float) * 12 * (size_t)nv; }
+size_t laplace_smooth_workspace(int nv) { return sizeof(float) * 13 * (size_t)nv; }
 
-hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, float lam, const float* g,
-                                 float* out, float* ws, int max_iter, float tol, float* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_laplace_smooth, dim3(1), dim3(CG_T), 0, s, nv, adj_off, adj_nbr, lam, g, out, ws, max_iter,
-                     tol, info);
+hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, const int32_t* adj_tab,
+                                 float lam, const float* g, float* out, float* ws, int max_iter, float tol,
+                                 float* info, hipStream_t s) {
+  if (adj_tab != nullptr)
+    hipLaunchKernelGGL(k_laplace_smooth<true>, dim3(1), dim3(CG_T), 0, s, nv, adj_off, adj_nbr, adj_tab, lam, g, out,
+                       ws, max_iter, tol, info);
+  else
+    hipLaunchKernelGGL(k_laplace_smooth<false>, dim3(1), dim3(CG_T), 0, s, nv, adj_off, adj_nbr, adj_tab, lam, g,
+                       out, ws, max_iter, tol, info);
   return hipGetLastError();
 }
 

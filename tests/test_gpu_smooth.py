@@ -121,3 +121,21 @@ def test_open_mesh_and_errors(dm, handle):
     for kw in ({"lam": -1.0}, {"lam": float("nan")}, {"tol": 0.0}, {"max_iter": 0}):
         with pytest.raises(Exception):
             dm.laplace_smooth(handle, topo, dev(g), **kw)
+
+
+def test_high_degree_vertices_use_the_list_path(dm, handle):
+    """A 12-sided bipyramid: its apexes have degree 12, above the width of
+    the neighbour table, so the adjacency lists are used."""
+    n = 12
+    ang = 2 * np.pi * np.arange(n) / n
+    V = np.concatenate([np.stack([np.cos(ang), np.sin(ang), np.zeros(n)], 1), [[0, 0, 1.0], [0, 0, -1.0]]])
+    top, bot = n, n + 1
+    F = np.array([[i, (i + 1) % n, top] for i in range(n)] + [[(i + 1) % n, i, bot] for i in range(n)])
+    assert meshes.check_closed_oriented(F)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal((n + 2, 3)).astype(np.float32)
+    topo = handle.topology(F, n_verts=n + 2)
+    got = dm.laplace_smooth(handle, topo, dev(g), lam=50.0, tol=1e-7).cpu().numpy()
+    err = rel(got, S.laplace_smooth(F, n + 2, g.astype(np.float64), 50.0))
+    say("bipyramid (degree 12) rel", err)
+    assert err < 1e-4
