@@ -20,6 +20,11 @@
  *    exact definition as the corner entry of exp of a bidiagonal matrix
  *    (Opitz' theorem), computed by scaling and squaring.
  *  - Surface density, Eq. 5-6 (normalised by |Lambda| in the Python layer).
+ *  - Several surfaces or materials (Sec. 3.3: a weighted sum of densities;
+ *    cell-cell interfaces as double membranes): every triangle carries a
+ *    density weight w_T (1 when no weights are given) that multiplies its
+ *    contribution; the surface normalisation becomes sum_T w_T A_T, and for
+ *    the indicator density w_T is the density jump across the triangle.
  *  - Indicator density: by the divergence theorem
  *      chi(xi) = (i/|xi|^2) sum_T (xi . n_T) f_T(xi),  n_T = (v2-v1)x(v3-v1),
  *    and chi(0) = enclosed volume.  Its vertex gradient is the boundary
@@ -155,6 +160,7 @@ typedef struct {
   double n[3];      /* (v2-v1)x(v3-v1) = 2 A_T N_T */
   double twoA;      /* 2 A_T */
   double w[3][3];   /* w_p = e_p x N_T (zero for a zero-area triangle) */
+  double wt;        /* density weight of the triangle */
 } tri_geom;
 
 static void build_geom(const double* V, const int* F, int t, tri_geom* g) {
@@ -182,25 +188,29 @@ static void phases(const tri_geom* g, const double xi[3], double y[3]) {
 /* Mesh transform at nk frequencies.
  * mode 0 (indicator):  chi(xi) (enclosed volume at xi = 0).
  * mode 1 (surface):    sum_T u_T(xi) = sum_T 2 A_T f_T  (not yet divided by |Lambda|).
+ * Each triangle's term is multiplied by tri_w[t] (tri_w NULL: by 1).
  * V: [nv][3] positions relative to the grid origin; F: [nt][3]; xi: [nk][3]. */
-void oracle_mesh_ft(int mode, const double* V, int nv, const int* F, int nt,
+void oracle_mesh_ft(int mode, const double* V, int nv, const int* F, int nt, const double* tri_w,
                     const double* xi, int nk, double* out_re_im) {
   (void)nv;
   tri_geom* G = (tri_geom*)malloc(sizeof(tri_geom) * (size_t)(nt > 0 ? nt : 1));
-  for (int t = 0; t < nt; ++t) build_geom(V, F, t, &G[t]);
+  for (int t = 0; t < nt; ++t) {
+    build_geom(V, F, t, &G[t]);
+    G[t].wt = tri_w ? tri_w[t] : 1.0;
+  }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int k = 0; k < nk; ++k) {
     const double* x = xi + 3 * k;
     double q2 = dot3(x, x);
     cplx s = 0;
     if (mode == 0 && q2 == 0.0) {
-      for (int t = 0; t < nt; ++t) s += dot3(G[t].v[0], G[t].n) / 6.0;
+      for (int t = 0; t < nt; ++t) s += G[t].wt * dot3(G[t].v[0], G[t].n) / 6.0;
     } else {
       for (int t = 0; t < nt; ++t) {
         double y[3];
         phases(&G[t], x, y);
         cplx f = tri_f(y);
-        s += (mode == 0 ? dot3(x, G[t].n) : G[t].twoA) * f;
+        s += G[t].wt * (mode == 0 ? dot3(x, G[t].n) : G[t].twoA) * f;
       }
       if (mode == 0) s *= I / q2;
     }
@@ -213,12 +223,18 @@ void oracle_mesh_ft(int mode, const double* V, int nv, const int* F, int nt,
 /* Vertex gradient of L = sum_k Re[ W_k * u(xi_k) ] where u is
  *   mode 0: chi(xi);   mode 1: the normalised surface transform of Eq. 5.
  * For mode 1 the normalisation term of Eq. 6 needs u at every xi_k, which the
- * routine evaluates itself.  dV: [nv][3], overwritten. */
-void oracle_mesh_ft_vjp(int mode, const double* V, int nv, const int* F, int nt,
+ * routine evaluates itself.  With density weights (tri_w, NULL for 1) the
+ * transforms are the weighted sums of oracle_mesh_ft and mode 1 divides by
+ * sum_T w_T A_T.  dV: [nv][3], overwritten. */
+void oracle_mesh_ft_vjp(int mode, const double* V, int nv, const int* F, int nt, const double* tri_w,
                         const double* xi, const double* W_re_im, int nk, double* dV) {
   tri_geom* G = (tri_geom*)malloc(sizeof(tri_geom) * (size_t)(nt > 0 ? nt : 1));
   double area = 0;
-  for (int t = 0; t < nt; ++t) { build_geom(V, F, t, &G[t]); area += 0.5 * G[t].twoA; }
+  for (int t = 0; t < nt; ++t) {
+    build_geom(V, F, t, &G[t]);
+    G[t].wt = tri_w ? tri_w[t] : 1.0;
+    area += G[t].wt * 0.5 * G[t].twoA;
+  }
   memset(dV, 0, sizeof(double) * 3 * (size_t)nv);
   int nthreads = 1;
 #ifdef _OPENMP
@@ -246,7 +262,7 @@ void oracle_mesh_ft_vjp(int mode, const double* V, int nv, const int* F, int nt,
           tri_dfdv(y, B);
           for (int p = 0; p < 3; ++p) {
             /* DD4_p = i B_p ;  d chi / d v_p = n_T DD4_p */
-            double r = creal(W * (I * B[p]));
+            double r = G[t].wt * creal(W * (I * B[p]));
             int v = F[3 * t + p];
             for (int j = 0; j < 3; ++j) a[3 * v + j] += r * G[t].n[j];
           }
@@ -259,7 +275,7 @@ void oracle_mesh_ft_vjp(int mode, const double* V, int nv, const int* F, int nt,
           double y[3];
           phases(&G[t], x, y);
           fT[t] = tri_f(y);
-          u += G[t].twoA * fT[t];
+          u += G[t].wt * G[t].twoA * fT[t];
         }
         u /= area;
         for (int t = 0; t < nt; ++t) {
@@ -272,7 +288,7 @@ void oracle_mesh_ft_vjp(int mode, const double* V, int nv, const int* F, int nt,
             for (int j = 0; j < 3; ++j) {
               cplx duT = -fT[t] * G[t].w[p][j] + G[t].twoA * x[j] * B[p];
               cplx dA = -0.5 * G[t].w[p][j];
-              a[3 * v + j] += creal(W * (duT - u * dA)) / area;
+              a[3 * v + j] += G[t].wt * creal(W * (duT - u * dA)) / area;
             }
           }
         }

@@ -61,8 +61,8 @@ def _c():
         L = ctypes.CDLL(str(LIB))
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
-        L.oracle_mesh_ft.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, dp]
-        L.oracle_mesh_ft_vjp.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp,
+        L.oracle_mesh_ft.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp, ctypes.c_int, dp]
+        L.oracle_mesh_ft_vjp.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ctypes.c_int, dp, dp, dp,
                                          ctypes.c_int, dp]
         L.oracle_cone_volume_ft.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, dp, ctypes.c_int, dp]
         L.oracle_dd_exp.argtypes = [dp, ctypes.c_int, dp]
@@ -122,16 +122,28 @@ def tri_dfdv(y) -> np.ndarray:
     return out[0::2] + 1j * out[1::2]
 
 
-def mesh_ft_raw(V, F, xi, mode: int) -> np.ndarray:
+def _weights(tri_w, nt):
+    if tri_w is None:
+        return None, None
+    w = _d(tri_w).reshape(-1)
+    if w.shape[0] != nt:
+        raise ValueError("one density weight per triangle")
+    return w, _p(w, ctypes.c_double)
+
+
+def mesh_ft_raw(V, F, xi, mode: int, tri_w=None) -> np.ndarray:
     """VOLUME: indicator transform chi(xi); SURFACE: sum_T 2 A_T f_T (unnormalised).
 
-    ``V`` are positions relative to the phase origin, ``xi`` is [..., 3]."""
+    ``V`` are positions relative to the phase origin, ``xi`` is [..., 3];
+    ``tri_w`` (optional) are per-triangle density weights multiplying each
+    triangle's term."""
     V, F = _d(V), _i(F)
     xi = _d(xi)
     shape = xi.shape[:-1]
     xi = xi.reshape(-1, 3)
     out = np.zeros(2 * xi.shape[0])
-    _c().oracle_mesh_ft(int(mode), _p(V, ctypes.c_double), V.shape[0], _p(F, ctypes.c_int), F.shape[0],
+    w, wp = _weights(tri_w, F.shape[0])
+    _c().oracle_mesh_ft(int(mode), _p(V, ctypes.c_double), V.shape[0], _p(F, ctypes.c_int), F.shape[0], wp,
                         _p(xi, ctypes.c_double), xi.shape[0], _p(out, ctypes.c_double))
     return (out[0::2] + 1j * out[1::2]).reshape(shape)
 
@@ -150,24 +162,28 @@ def cone_volume_ft(V, F, xi, c=None) -> np.ndarray:
     return (out[0::2] + 1j * out[1::2]).reshape(shape)
 
 
-def mesh_ft_vjp_raw(V, F, xi, W, mode: int) -> np.ndarray:
+def mesh_ft_vjp_raw(V, F, xi, W, mode: int, tri_w=None) -> np.ndarray:
     """Gradient with respect to V of sum_k Re[W_k u(xi_k)], where u is the
-    indicator transform (VOLUME) or the normalised surface transform (SURFACE)."""
+    indicator transform (VOLUME) or the normalised surface transform (SURFACE),
+    both weighted by ``tri_w`` when given."""
     V, F = _d(V), _i(F)
     xi = _d(xi).reshape(-1, 3)
     W = np.asarray(W, dtype=np.complex128).reshape(-1)
     Wb = _d(np.stack([W.real, W.imag], axis=1).ravel())
     dV = np.zeros((V.shape[0], 3))
-    _c().oracle_mesh_ft_vjp(int(mode), _p(V, ctypes.c_double), V.shape[0], _p(F, ctypes.c_int), F.shape[0],
+    w, wp = _weights(tri_w, F.shape[0])
+    _c().oracle_mesh_ft_vjp(int(mode), _p(V, ctypes.c_double), V.shape[0], _p(F, ctypes.c_int), F.shape[0], wp,
                             _p(xi, ctypes.c_double), _p(Wb, ctypes.c_double), xi.shape[0],
                             _p(dV, ctypes.c_double))
     return dV
 
 
-def surface_area(V, F) -> float:
+def surface_area(V, F, tri_w=None) -> float:
+    """sum_T A_T, or sum_T w_T A_T with density weights."""
     V = _d(V)
     n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
-    return float(0.5 * np.linalg.norm(n, axis=1).sum())
+    a = 0.5 * np.linalg.norm(n, axis=1)
+    return float(a.sum() if tri_w is None else (a * _d(tri_w)).sum())
 
 
 # ---------------------------------------------------------------- frequencies
@@ -226,16 +242,16 @@ def otf_and_band(grid, sigma6, K=None):
 
 
 # ---------------------------------------------------------------- pipeline
-def mesh_transform(V, F, xi, grid, mode: int) -> np.ndarray:
+def mesh_transform(V, F, xi, grid, mode: int, tri_w=None) -> np.ndarray:
     """u(xi) for positions V in the grid frame (phase origin = grid origin)."""
     Vr = _d(V) - np.asarray(grid.origin, dtype=np.float64)
-    u = mesh_ft_raw(Vr, F, xi, mode)
+    u = mesh_ft_raw(Vr, F, xi, mode, tri_w)
     if mode == SURFACE:
-        u = u / surface_area(V, F)
+        u = u / surface_area(V, F, tri_w)
     return u
 
 
-def spectrum(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None):
+def spectrum(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None, tri_w=None):
     """Full-grid spectrum I_hat = h u on the band (zero elsewhere).
 
     ``band_sigma6`` (default: ``sigma6``) selects the covariance that decides
@@ -246,18 +262,18 @@ def spectrum(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None):
         band = otf_and_band(grid, band_sigma6)[2]
     u = np.zeros(grid.n, dtype=np.complex128)
     if band.any():
-        u[band] = mesh_transform(V, F, xi[band], grid, mode)
+        u[band] = mesh_transform(V, F, xi[band], grid, mode, tri_w)
     return h * u * band, (xi, h, band, u)
 
 
-def render(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None) -> np.ndarray:
+def render(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None, tri_w=None) -> np.ndarray:
     """Image on the grid: Re(ifftn(I_hat)) / (Dx Dy Dz)."""
-    Ihat, _ = spectrum(V, F, grid, sigma6, mode, band_sigma6)
+    Ihat, _ = spectrum(V, F, grid, sigma6, mode, band_sigma6, tri_w)
     dvol = float(grid.spacing[0]) * float(grid.spacing[1]) * float(grid.spacing[2])
     return np.real(np.fft.ifftn(Ihat)) / dvol
 
 
-def render_vjp(V, F, grid, sigma6, dL_dI, mode: int | None = None):
+def render_vjp(V, F, grid, sigma6, dL_dI, mode: int | None = None, tri_w=None):
     """Gradients (dL/dV [n_v,3], dL/dSigma [6]) for a given dL/dI [N0,N1,N2].
 
     dL/dtheta = (1/(Lx Ly Lz)) sum_{k in band} Re[ conj(G_k) d(I_hat_k)/dtheta ],
@@ -271,8 +287,8 @@ def render_vjp(V, F, grid, sigma6, dL_dI, mode: int | None = None):
     xb, hb, Gb = xi[band], h[band], G[band]
     W = np.conj(Gb) * hb / LV
     Vr = _d(V) - np.asarray(grid.origin, dtype=np.float64)
-    dV = mesh_ft_vjp_raw(Vr, F, xb, W, mode) if band.any() else np.zeros((len(V), 3))
-    u = mesh_transform(V, F, xb, grid, mode) if band.any() else np.zeros(0, complex)
+    dV = mesh_ft_vjp_raw(Vr, F, xb, W, mode, tri_w) if band.any() else np.zeros((len(V), 3))
+    u = mesh_transform(V, F, xb, grid, mode, tri_w) if band.any() else np.zeros(0, complex)
     base = np.real(np.conj(Gb) * u * hb) / LV
     pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
     dS = np.zeros(6)

@@ -189,3 +189,84 @@ def check_closed_oriented(F: np.ndarray) -> bool:
     if len(fwd) != len(e):
         return False
     return all((b, a) in fwd for a, b in fwd)
+
+
+def cube_foam(cells=(2, 2, 2), sub: int = 4, size: float = 1.0):
+    """A cluster of box-shaped cells sharing their walls: the non-manifold,
+    multimaterial mesh of a cell aggregate (one copy of every wall).
+
+    The block [0, cells_x] x [0, cells_y] x [0, cells_z] (times ``size``) is
+    cut into unit cells; every cell face is split into sub x sub squares of
+    two triangles.  Returns ``(V, F, side)`` with ``side[t] = (a, b)`` the
+    cells behind and in front of triangle t: its normal (counter-clockwise
+    order) points from cell a into cell b, and -1 stands for the outside.
+    Walls between two cells appear once; outer faces point outward."""
+    nc = np.asarray(cells, dtype=np.int64)
+    res = nc * sub + 1
+    index = {}
+    verts = []
+
+    def vid(p):
+        key = tuple(int(x) for x in p)
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(key)
+        return index[key]
+
+    def cell_id(c):
+        if any(c[j] < 0 or c[j] >= nc[j] for j in range(3)):
+            return -1
+        return int((c[0] * nc[1] + c[1]) * nc[2] + c[2])
+
+    faces, side = [], []
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for plane in range(nc[a] + 1):
+            for cb in range(nc[b]):
+                for cc in range(nc[c]):
+                    lo_cell = [0, 0, 0]
+                    lo_cell[a], lo_cell[b], lo_cell[c] = plane - 1, cb, cc
+                    hi_cell = list(lo_cell)
+                    hi_cell[a] = plane
+                    back, front = cell_id(lo_cell), cell_id(hi_cell)
+                    flip = back < 0          # outer face at the low end: normal along -a
+                    if flip:
+                        back, front = front, back
+                    for i in range(sub):
+                        for j in range(sub):
+                            q = []
+                            for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                                p = [0, 0, 0]
+                                p[a] = plane * sub
+                                p[b] = cb * sub + i + di
+                                p[c] = cc * sub + j + dj
+                                q.append(vid(p))
+                            # (b, c) counter-clockwise seen from +a: normal along +a
+                            tris = [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+                            for t in tris:
+                                faces.append((t[0], t[2], t[1]) if flip else t)
+                                side.append((back, front))
+    V = np.asarray(verts, dtype=np.float64) * (size / sub)
+    return V, np.asarray(faces, dtype=np.int64), np.asarray(side, dtype=np.int64)
+
+
+def foam_deform(V: np.ndarray, rng: np.random.Generator, round_by: float = 0.5, wobble: float = 0.04):
+    """Smooth deformation of a cube foam into a rounded cell cluster: points
+    are pulled towards the sphere through the block's corners by ``round_by``
+    (0: unchanged) and moved by a low-frequency random field of relative
+    amplitude ``wobble``.  The map is one-to-one for these amplitudes, so
+    the connectivity and the orientation of the foam stay valid."""
+    c = 0.5 * (V.min(0) + V.max(0))
+    d = V - c
+    half = 0.5 * (V.max(0) - V.min(0))
+    u = d / half                                   # block -> [-1, 1]^3
+    n_inf = np.abs(u).max(axis=1)
+    n_2 = np.linalg.norm(u, axis=1)
+    scale = np.ones(len(V))
+    nz = n_2 > 0
+    scale[nz] = (1.0 - round_by) + round_by * n_inf[nz] / n_2[nz]
+    u = u * scale[:, None]
+    k = rng.normal(size=(3, 3)) * 1.5
+    ph = rng.uniform(0, 2 * np.pi, size=3)
+    u = u + wobble * np.sin(u @ k + ph)
+    return c + u * half
