@@ -129,6 +129,26 @@ dm_status dm_topology_destroy(dm_topology* t);
 /* closed = 1 if closed and consistently oriented. */
 dm_status dm_topology_info(const dm_topology* t, int32_t* n_faces, int32_t* n_verts, int32_t* closed);
 
+/* Density weights of the faces (paper Sec. 3.3: several surfaces or
+ * materials rendered as a weighted sum of densities; cell-cell interfaces
+ * modelled as double membranes).  weights: host [n_faces] float32 in the
+ * order of the faces given to dm_topology_create; NULL removes them (every
+ * face weighs 1).  Each face's term of the mesh transform is multiplied by its
+ * weight:
+ *   DM_SURFACE: u = sum_T w_T 2 A_T f_T / sum_T w_T A_T (w_T = 2 for a wall
+ *     shared by two cells of a non-manifold cluster mesh, 1 elsewhere);
+ *   DM_VOLUME: w_T is the density jump across face T (density behind minus
+ *     density in front of its counter-clockwise normal), so that the weighted
+ *     divergence sum is the transform of a piecewise-constant density.  Such
+ *     weights cancel across every edge (sum of the weights of the faces on
+ *     the edge, signed by the direction each face runs along it); the
+ *     topology is then reported closed and accepted by DM_VOLUME, otherwise
+ *     DM_VOLUME renders fail with DM_ERR_MESH.
+ * The vertex gradients and the PSF gradient follow.  Synchronises the device
+ * (the weights are copied to it).  Errors: DM_ERR_ARG for a NULL topology or
+ * a weight that is not finite. */
+dm_status dm_topology_set_weights(dm_topology* t, const float* weights);
+
 /* Smoothed update direction of the shape step (paper Sec. 5.2): the vertex
  * gradient filtered twice by the inverse of I + lambda L,
  *     out = (I + lambda L)^{-2} grad,

@@ -106,6 +106,7 @@ def _load():
         "dm_topology_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "dm_topology_strips": [vp, i32, vp, vp, ctypes.POINTER(i32)],
         "dm_laplace_smooth": [vp, vp, ctypes.c_float, vp, vp, i32, ctypes.c_float, vp, vp],
+        "dm_topology_set_weights": [vp, vp],
         "dm_band_size": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), ctypes.POINTER(i64), vp],
         "dm_band_export": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), vp, vp, vp, vp],
         "dm_render": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CPsf), ctypes.POINTER(CGrid), vp, vp, vp],
@@ -270,6 +271,21 @@ class Topology:
         _check(L.dm_topology_create(handle.ptr, ctypes.c_void_p(ptr), int(nf), int(nv), on_dev, ctypes.byref(self._t)),
                "dm_topology_create")
         self.n_faces, self.n_verts = int(nf), int(nv)
+        c = ctypes.c_int32()
+        _check(L.dm_topology_info(self._t, None, None, ctypes.byref(c)), "dm_topology_info")
+        self.closed = bool(c.value)
+
+    def set_weights(self, weights=None):
+        """Per-face density weights (input face order) or None for all 1;
+        updates ``closed`` (weighted closure for the indicator density)."""
+        L = _load()
+        if weights is None:
+            _check(L.dm_topology_set_weights(self._t, None), "dm_topology_set_weights")
+        else:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).reshape(-1))
+            if w.shape[0] != self.n_faces:
+                raise ValueError(f"need {self.n_faces} weights")
+            _check(L.dm_topology_set_weights(self._t, ctypes.c_void_p(w.ctypes.data)), "dm_topology_set_weights")
         c = ctypes.c_int32()
         _check(L.dm_topology_info(self._t, None, None, ctypes.byref(c)), "dm_topology_info")
         self.closed = bool(c.value)

@@ -140,6 +140,11 @@ struct dm_topology {
   int32_t* adj_off = nullptr;   // device [nv+1]: vertex adjacency (mesh edges), CSR
   int32_t* adj_nbr = nullptr;   // device [2 n_edges]
   int32_t* adj_tab = nullptr;   // device [nv][LAP_TABLE_W], -1 padded; nullptr if a degree exceeds the width
+  // density weights (dm_topology_set_weights): device [nt] in strip order, or nullptr (all 1)
+  float* weights = nullptr;
+  int closed_plain = 0;                    // closed and consistently oriented, ignoring weights
+  std::vector<int32_t> faces_in;           // host copy of the input faces
+  std::vector<int32_t> src;                // input face of each strip-order triangle
   size_t bytes = 0;
   float* smooth_ws = nullptr;   // device workspace of dm_laplace_smooth (allocated on first use)
   size_t smooth_bytes = 0;
@@ -391,7 +396,8 @@ dm_status check_mesh(const dm_mesh* m, int mode) {
 // triangle across it is unused; of the seed's three rotations the longest
 // strip is kept.  Output: faces in strip order (s_i, s_i+1, s_i+2) and flags
 // (strip start; odd permutation of the input face, i.e. reversed orientation).
-int build_strips(const std::vector<int32_t>& F, std::vector<int32_t>& Fs, std::vector<int32_t>& flags) {
+int build_strips(const std::vector<int32_t>& F, std::vector<int32_t>& Fs, std::vector<int32_t>& flags,
+                 std::vector<int32_t>* src = nullptr) {
   const int nt = (int)(F.size() / 3);
   std::vector<std::pair<uint64_t, int>> edges;
   edges.reserve(F.size());
@@ -421,6 +427,10 @@ int build_strips(const std::vector<int32_t>& F, std::vector<int32_t>& Fs, std::v
   flags.clear();
   Fs.reserve(F.size());
   flags.reserve((size_t)nt);
+  if (src) {
+    src->clear();
+    src->reserve((size_t)nt);
+  }
   int n_strips = 0;
   std::vector<int> tris, best_tris;
   std::vector<int32_t> seq, best_seq;
@@ -457,6 +467,7 @@ int build_strips(const std::vector<int32_t>& F, std::vector<int32_t>& Fs, std::v
       for (int r = 0; r < 3; ++r)
         same = same || (F[3 * u + r] == a && F[3 * u + (r + 1) % 3] == b && F[3 * u + (r + 2) % 3] == c);
       flags.push_back((i == 0 ? TRI_STRIP_START : 0) | (same ? 0 : TRI_REVERSED));
+      if (src) src->push_back(u);
     }
     ++n_strips;
   }
@@ -662,7 +673,8 @@ dm_status stage_pre(dm_handle* h, ReqPlan& P, hipStream_t s) {
     DM_TRY(zero_fill(P.dS, 6, s));
     return DM_OK;
   }
-  HIP_TRY(launch_mesh_prep(P.mode, P.gc, P.m->verts_dev, P.nv, P.m->topo->faces, P.m->topo->flags, P.nt, P.ptr<float>(P.o_rec),
+  HIP_TRY(launch_mesh_prep(P.mode, P.gc, P.m->verts_dev, P.nv, P.m->topo->faces, P.m->topo->flags, P.m->topo->weights,
+                           P.nt, P.ptr<float>(P.o_rec),
                            P.ptr<MeshInfo>(P.o_info), P.ptr<double>(P.o_ptmp), P.prep_blocks, s));
   if (P.want_vjp) {
     HIP_TRY(hipMemcpyAsync(P.ptr<float>(P.o_gin), P.dLdI, (size_t)P.nvox * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -756,7 +768,8 @@ dm_status stage_post(dm_handle* h, ReqPlan& P, hipStream_t s) {
     HIP_TRY(launch_vjp_reduce(P.mode, P.ptr<float>(P.o_vpart), P.vsp.n_chunks, P.nt, P.ptr<float>(P.o_rtmp), red, s));
     double* R = P.ptr<double>(P.o_R);
     if (P.mode == DM_SURFACE) HIP_TRY(launch_surface_scalar(red, P.ptr<float>(P.o_rec), P.nt, info, R, s));
-    HIP_TRY(launch_vertex_gather(P.mode, P.m->verts_dev, P.nv, P.m->topo->faces, P.m->topo->flags, P.nt, P.m->topo->csr_off,
+    HIP_TRY(launch_vertex_gather(P.mode, P.m->verts_dev, P.nv, P.m->topo->faces, P.m->topo->flags, P.m->topo->weights,
+                                 P.nt, P.m->topo->csr_off,
                                  P.m->topo->csr_ent, red, R, P.dV, s));
   }
   return DM_OK;
@@ -999,8 +1012,9 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
         break;
       }
     }
-  std::vector<int32_t> Fs, fl;
-  const int n_strips = build_strips(F, Fs, fl);
+  std::vector<int32_t> Fs, fl, src;
+  const int n_strips = build_strips(F, Fs, fl, &src);
+  std::vector<int32_t> faces_in = F;
   F.swap(Fs);
   // vertex incidence (CSR)
   std::vector<int32_t> off((size_t)n_verts + 1, 0), ent(F.size());
@@ -1038,7 +1052,10 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
   t->nt = n_faces;
   t->nv = n_verts;
   t->closed = closed ? 1 : 0;
+  t->closed_plain = t->closed;
   t->n_strips = n_strips;
+  t->faces_in.swap(faces_in);
+  t->src.swap(src);
   const size_t bf = align_up(F.size() * 4), bo = align_up(off.size() * 4), be = align_up(ent.size() * 4),
                bl = align_up(fl.size() * 4), bao = align_up(aoff.size() * 4), ban = align_up(anbr.size() * 4),
                bat = align_up(atab.size() * 4);
@@ -1095,6 +1112,7 @@ dm_status dm_topology_destroy(dm_topology* t) {
   (void)hipDeviceSynchronize();
   dev_free(t->h, t->faces, t->bytes);
   dev_free(t->h, t->smooth_ws, t->smooth_bytes);
+  dev_free(t->h, t->weights, align_up((size_t)t->nt * 4));
   t->h->topo_count--;
   delete t;
   return DM_OK;
@@ -1120,6 +1138,55 @@ dm_status dm_laplace_smooth(dm_handle* h, dm_topology* t, float lambda, const fl
   }
   HIP_TRY(launch_laplace_smooth(t->nv, t->adj_off, t->adj_nbr, t->adj_tab, lambda, grad, out, t->smooth_ws, max_iter,
                                 tol, info, static_cast<hipStream_t>(stream)));
+  return DM_OK;
+}
+
+dm_status dm_topology_set_weights(dm_topology* t, const float* weights) {
+  g_err.clear();
+  if (!t) return fail(DM_ERR_ARG, "topology is NULL");
+  DeviceGuard dg(t->h->device);
+  if (!weights) {
+    (void)hipDeviceSynchronize();
+    dev_free(t->h, t->weights, align_up((size_t)t->nt * 4));
+    t->weights = nullptr;
+    t->closed = t->closed_plain;
+    return DM_OK;
+  }
+  for (int i = 0; i < t->nt; ++i)
+    if (!std::isfinite(weights[i])) return fail(DM_ERR_ARG, "weight of face %d is not finite", i);
+  // weighted closure: across every edge the weights of the incident faces,
+  // signed by the direction in which each face runs along the edge, cancel
+  std::vector<std::pair<uint64_t, std::pair<double, double>>> e;   // edge -> (signed sum, sum of |w|)
+  e.reserve((size_t)t->nt * 3);
+  for (int f = 0; f < t->nt; ++f)
+    for (int p = 0; p < 3; ++p) {
+      const uint32_t a = (uint32_t)t->faces_in[3 * f + p], b = (uint32_t)t->faces_in[3 * f + (p + 1) % 3];
+      const double w = weights[f];
+      const uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
+      e.push_back({key, {a < b ? w : -w, std::fabs(w)}});
+    }
+  std::sort(e.begin(), e.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+  bool closed = t->nt > 0;
+  for (size_t i = 0; i < e.size() && closed;) {
+    size_t j = i;
+    double sum = 0.0, mag = 0.0;
+    for (; j < e.size() && e[j].first == e[i].first; ++j) {
+      sum += e[j].second.first;
+      mag += e[j].second.second;
+    }
+    if (std::fabs(sum) > 1e-6 * mag) closed = false;
+    i = j;
+  }
+  std::vector<float> ws((size_t)t->nt);
+  for (int i = 0; i < t->nt; ++i) ws[(size_t)i] = weights[t->src[(size_t)i]];
+  if (!t->weights) {
+    void* mem = nullptr;
+    DM_TRY(dev_alloc(t->h, &mem, align_up((size_t)t->nt * 4)));
+    t->weights = static_cast<float*>(mem);
+  }
+  (void)hipDeviceSynchronize();
+  if (t->nt > 0) HIP_TRY(hipMemcpy(t->weights, ws.data(), ws.size() * 4, hipMemcpyHostToDevice));
+  t->closed = closed ? 1 : 0;
   return DM_OK;
 }
 
@@ -1265,7 +1332,8 @@ dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g,
   DM_TRY(ensure_ws(h, cv.off));
   float* rec = at<float>(h, o_rec);
   MeshInfo* info = at<MeshInfo>(h, o_info);
-  HIP_TRY(launch_mesh_prep(mode, gc, mesh->verts_dev, mesh->n_verts, mesh->topo->faces, mesh->topo->flags, nt, rec, info,
+  HIP_TRY(launch_mesh_prep(mode, gc, mesh->verts_dev, mesh->n_verts, mesh->topo->faces, mesh->topo->flags,
+                           mesh->topo->weights, nt, rec, info,
                            at<double>(h, o_ptmp), prep_blocks, s));
   float4* kf = at<float4>(h, o_kf);
   HIP_TRY(launch_points_prepare(gc, k_dev, n, kf, s));

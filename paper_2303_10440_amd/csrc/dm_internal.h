@@ -99,8 +99,9 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_band_fill(const GridC& g, const double* sigma6, double qmax, const int32_t* cnt,
                             const int32_t* off, int64_t n_slots, BandDev b, hipStream_t s);
 
+// tri_w: per-triangle density weights in strip order, or nullptr (all 1).
 hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces,
-                            const int32_t* flags, int nt,
+                            const int32_t* flags, const float* tri_w, int nt,
                             float* tri_rec, MeshInfo* info, double* block_tmp, int tmp_blocks, hipStream_t s);
 int mesh_prep_blocks(int nt);
 
@@ -134,7 +135,7 @@ hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, 
 hipError_t launch_surface_scalar(const float* red, const float* tri_rec, int nt, const MeshInfo* info,
                                  double* out_R, hipStream_t s);
 hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, const int32_t* flags,
-                                int nt,
+                                const float* tri_w, int nt,
                                 const int32_t* csr_off, const int32_t* csr_ent, const float* red,
                                 const double* R, float* dV, hipStream_t s);
 

@@ -502,7 +502,8 @@ __global__ void __launch_bounds__(PREP_T) k_prep_centroid(GridC g, const float* 
 template <int MODE>
 __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __restrict__ V,
                                                         const int32_t* __restrict__ F,
-                                                        const int32_t* __restrict__ flags, int nt,
+                                                        const int32_t* __restrict__ flags,
+                                                        const float* __restrict__ tri_w, int nt,
                                                         const MeshInfo* __restrict__ info,
                                                         float* __restrict__ rec, double* __restrict__ tmp) {
   __shared__ double sh[PREP_T];
@@ -518,6 +519,8 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
     double e2[3], e3[3], a[3], b[3];
     const int fl = flags[t];
     const double sgn = (fl & TRI_REVERSED) ? -1.0 : 1.0;
+    // density weight (several materials or double membranes); 1 without weights
+    const double wt = tri_w != nullptr ? (double)tri_w[t] : 1.0;
     for (int j = 0; j < 3; ++j) {
       const double u = (v[2][j] - c[j]) / g.L[j];
       const double uh = rint(u * (double)PHASE_GRID) / (double)PHASE_GRID;
@@ -534,17 +537,17 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
                          sgn * (e2[0] * e3[1] - e2[1] * e3[0])};
     const double twoA = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     if (MODE == 0) {
-      for (int j = 0; j < 3; ++j) r[12 + j] = (float)(n[j] / (g.L[j] * TWO_PI_D * TWO_PI_D));
+      for (int j = 0; j < 3; ++j) r[12 + j] = (float)(wt * n[j] / (g.L[j] * TWO_PI_D * TWO_PI_D));
     } else {
-      r[12] = (float)twoA;
+      r[12] = (float)(wt * twoA);
       r[13] = 0.0f;
       r[14] = 0.0f;
     }
     r[15] = (fl & TRI_STRIP_START) ? 1.0f : 0.0f;
-    area += 0.5 * twoA;
+    area += wt * 0.5 * twoA;
     const double a0[3] = {v[0][0] - c[0], v[0][1] - c[1], v[0][2] - c[2]};
-    vol += sgn * (a0[0] * (a[1] * b[2] - a[2] * b[1]) + a0[1] * (a[2] * b[0] - a[0] * b[2]) +
-                  a0[2] * (a[0] * b[1] - a[1] * b[0])) / 6.0;
+    vol += wt * sgn * (a0[0] * (a[1] * b[2] - a[2] * b[1]) + a0[1] * (a[2] * b[0] - a[0] * b[2]) +
+                       a0[2] * (a[0] * b[1] - a[1] * b[0])) / 6.0;
   }
   area = block_sum(area, sh);
   vol = block_sum(vol, sh);
@@ -1288,7 +1291,8 @@ __global__ void k_vjp_reduce_final(const float* __restrict__ tmp, int groups, in
   red[i] = s;
 }
 
-// R = (1/|Lambda|) sum_T 2 A_T s_T  (surface normalisation term of Eq. 6)
+// R = (1/|Lambda|) sum_T 2 A_T s_T  (surface normalisation term of Eq. 6; with density
+// weights the record carries w_T 2 A_T and |Lambda| is sum_T w_T A_T)
 __global__ void __launch_bounds__(PREP_T) k_surface_scalar(const float* __restrict__ red,
                                                              const float* __restrict__ rec, int nt,
                                                              const MeshInfo* __restrict__ info,
@@ -1302,7 +1306,7 @@ __global__ void __launch_bounds__(PREP_T) k_surface_scalar(const float* __restri
 
 template <int MODE>
 __global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32_t* __restrict__ F,
-                                const int32_t* __restrict__ flags, int nt,
+                                const int32_t* __restrict__ flags, const float* __restrict__ tri_w, int nt,
                                 const int32_t* __restrict__ off, const int32_t* __restrict__ ent,
                                 const float* __restrict__ red, const double* __restrict__ Rp,
                                 float* __restrict__ dV) {
@@ -1313,6 +1317,7 @@ __global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32
   for (int i = off[v]; i < off[v + 1]; ++i) {
     const int tp = ent[i];
     const int t = tp / 3, p = tp - 3 * t;
+    const float wt = tri_w != nullptr ? tri_w[t] : 1.0f;
     float x[3][3];
     for (int q = 0; q < 3; ++q) {
       const int vi = F[3 * t + q];
@@ -1322,7 +1327,8 @@ __global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32
     const float b[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
     const float n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
     if (MODE == 0) {
-      const float Q = (flags[t] & TRI_REVERSED) ? -red[(size_t)p * nt + t] : red[(size_t)p * nt + t];
+      const float Qs = (flags[t] & TRI_REVERSED) ? -red[(size_t)p * nt + t] : red[(size_t)p * nt + t];
+      const float Q = wt * Qs;
       for (int j = 0; j < 3; ++j) g[j] = fmaf(n[j], Q, g[j]);
     } else {
       const float twoA = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
@@ -1334,7 +1340,7 @@ __global__ void k_vertex_gather(const float* __restrict__ V, int nv, const int32
       const float s = red[t];
       for (int j = 0; j < 3; ++j) {
         const float P = red[(size_t)(1 + 3 * p + j) * nt + t];
-        g[j] += twoA * P - w[j] * s + 0.5f * R * w[j];
+        g[j] += wt * (twoA * P - w[j] * s + 0.5f * R * w[j]);
       }
     }
   }
@@ -1411,14 +1417,14 @@ int mesh_prep_blocks(int nt) {
 }
 
 hipError_t launch_mesh_prep(int mode, const GridC& g, const float* verts, int nv, const int32_t* faces,
-                            const int32_t* flags, int nt,
+                            const int32_t* flags, const float* tri_w, int nt,
                             float* tri_rec, MeshInfo* info, double* block_tmp, int tmp_blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_prep_centroid, dim3(1), dim3(PREP_T), 0, s, g, verts, nv, info);
   if (mode == 0)
-    hipLaunchKernelGGL(k_prep_tris<0>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, flags, nt,
+    hipLaunchKernelGGL(k_prep_tris<0>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, flags, tri_w, nt,
                        (const MeshInfo*)info, tri_rec, block_tmp);
   else
-    hipLaunchKernelGGL(k_prep_tris<1>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, flags, nt,
+    hipLaunchKernelGGL(k_prep_tris<1>, dim3(tmp_blocks), dim3(PREP_T), 0, s, g, verts, faces, flags, tri_w, nt,
                        (const MeshInfo*)info, tri_rec, block_tmp);
   hipLaunchKernelGGL(k_prep_totals, dim3(1), dim3(PREP_T), 0, s, (const double*)block_tmp, tmp_blocks, info);
   return hipGetLastError();
@@ -1535,16 +1541,16 @@ hipError_t launch_surface_scalar(const float* red, const float* tri_rec, int nt,
 }
 
 hipError_t launch_vertex_gather(int mode, const float* verts, int nv, const int32_t* faces, const int32_t* flags,
-                                int nt,
+                                const float* tri_w, int nt,
                                 const int32_t* csr_off, const int32_t* csr_ent, const float* red,
                                 const double* R, float* dV, hipStream_t s) {
   const dim3 grid(blocks_for(nv, 128));
   if (mode == 0)
-    hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(128), 0, s, verts, nv, faces, flags, nt, csr_off, csr_ent, red, R,
-                       dV);
+    hipLaunchKernelGGL(k_vertex_gather<0>, grid, dim3(128), 0, s, verts, nv, faces, flags, tri_w, nt, csr_off, csr_ent,
+                       red, R, dV);
   else
-    hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(128), 0, s, verts, nv, faces, flags, nt, csr_off, csr_ent, red, R,
-                       dV);
+    hipLaunchKernelGGL(k_vertex_gather<1>, grid, dim3(128), 0, s, verts, nv, faces, flags, tri_w, nt, csr_off, csr_ent,
+                       red, R, dV);
   return hipGetLastError();
 }
 

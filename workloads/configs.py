@@ -172,3 +172,35 @@ def box_case(lo=(10.25, 11.5, 9.75), hi=(19.5, 17.25, 23.0), n=(32, 32, 32), mod
     V, F = meshes.box_mesh(lo, hi)
     g = Grid(tuple(n), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), tau, mode)
     return Case("box", _f32(V), _i32(F), g, psf_diag(sigma_xy, sigma_z))
+
+
+def foam_weights(side: np.ndarray, rho, mode: int) -> np.ndarray:
+    """Per-face density weights of a cell cluster from the cells on both
+    sides of every face (``meshes.cube_foam``): surface density, 2 on walls
+    between two cells (double membranes) and 1 on the outside; indicator
+    density, the jump rho(behind) - rho(in front), the outside at 0."""
+    if mode == SURFACE:
+        return np.where(side[:, 1] >= 0, 2.0, 1.0).astype(np.float32)
+    r = np.concatenate([np.asarray(rho, dtype=np.float64), [0.0]])
+    return (r[side[:, 0]] - r[side[:, 1]]).astype(np.float32)
+
+
+def foam_case(mode: int = SURFACE, seed: int = 0, cells=(2, 2, 2), sub: int = 8, n=(128, 128, 64),
+              spacing=(0.2, 0.2, 0.5), block: float = 12.0, sigma=(0.15, 0.45), tau: float = 1e-3,
+              name: str = "foam") -> Case:
+    """A cluster of cells sharing their walls (non-manifold, multimaterial):
+    a cube foam of ``cells`` box cells, every face split into sub x sub pairs
+    of triangles, rounded and wobbled smoothly, scaled to a block of
+    ``block`` length units and centred in the grid.  Defaults: 8 cells,
+    4608 triangles, in the single-cell grid (128 x 128 x 64 of 0.2 x 0.2 x
+    0.5 um, sigma (0.15, 0.15, 0.45) um).  ``extra``: the per-face weights for
+    ``mode`` (walls doubled for the surface density; for the indicator density
+    cell densities drawn from U[0.5, 1.5]), the face sides and the densities."""
+    rng = np.random.default_rng(seed)
+    g = Grid(tuple(n), tuple(float(s) for s in spacing), (0.0, 0.0, 0.0), tau, mode)
+    V, F, side = meshes.cube_foam(cells, sub=sub, size=1.0)
+    V = meshes.foam_deform(V, rng)
+    V = (V - 0.5 * (V.min(0) + V.max(0))) * (block / float(max(cells))) + g.centre
+    rho = rng.uniform(0.5, 1.5, size=int(np.prod(cells)))
+    w = foam_weights(side, rho, mode)
+    return Case(name, _f32(V), _i32(F), g, psf_diag(*sigma), {"tri_w": w, "side": side, "rho": rho})
