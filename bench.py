@@ -290,6 +290,41 @@ def bench_fit(dm, h, case, mode, shape_steps: int = 10, psf_steps: int = 4) -> d
             "psf": [float(x) for x in F.psf]}
 
 
+def bench_foam(dm, steps: int = 20) -> dict:
+    """The multi-cell workload: a cluster of 8 cells sharing their walls
+    (4608 faces, 2169 vertices) in the single-cell grid (128 x 128 x 64 of
+    0.2 x 0.2 x 0.5 um, sigma (0.15, 0.15, 0.45) um, band OTF > 1e-3), as the
+    paper's double-membrane surface density and as a piecewise-constant
+    indicator density (cell densities U[0.5, 1.5]); one dm_render_vjp per
+    step."""
+    import torch
+    from workloads import configs
+    h = dm.Handle(0)
+    out = {}
+    for mode, key in ((configs.SURFACE, "surface"), (configs.VOLUME, "volume")):
+        c = configs.foam_case(mode)
+        topo = h.topology(c.F, n_verts=len(c.V))
+        topo.set_weights(c.extra["tri_w"])
+        V = torch.tensor(c.V, device="cuda:0")
+        G = torch.tensor(np.random.default_rng(0).standard_normal(c.grid.n).astype(np.float32), device="cuda:0")
+        for _ in range(3):
+            dm.render_vjp(h, V, topo, c.sigma, c.grid, G, want_image=True)
+        torch.cuda.synchronize()
+        s_ = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s_)
+        for _ in range(steps):
+            dm.render_vjp(h, V, topo, c.sigma, c.grid, G, want_image=True)
+        e1.record(s_)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        pairs = float(dm.band_size(h, c.grid, c.sigma)) * c.F.shape[0]
+        out[key] = {"ms_per_step": ms, "pairs_per_step": pairs, "pairs_per_s": pairs / (ms * 1e-3)}
+    out["workload"] = ("8-cell cluster (cube foam 2x2x2, 8x8 squares per cell face, rounded), 4608 faces, "
+                       "walls once; 128x128x64 grid, 0.2x0.2x0.5 um, sigma (0.15, 0.15, 0.45) um, fwd + gradient")
+    return out
+
+
 def bench_smooth(dm, reps: int = 20) -> dict:
     """The shape step's Laplacian filter (I + 50 L)^{-2} g (dm_laplace_smooth)
     on the single-cell mesh (2562 vertices) and a 20252-vertex geodesic
@@ -399,6 +434,8 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true", help="add the 64-cell batched vs looped comparison")
     ap.add_argument("--sweeps", action="store_true",
                     help="add the paper's mesh-transform benchmark shapes (image size, triangle count)")
+    ap.add_argument("--foam", action="store_true",
+                    help="add the 8-cell cluster (per-face density weights) in both densities")
     ap.add_argument("--smooth", action="store_true",
                     help="add the shape step's Laplacian filter on the cell and a 20k-vertex sphere")
     ap.add_argument("--fit", action="store_true",
@@ -523,6 +560,8 @@ def main() -> int:
         out["sweeps_paper_shapes"] = bench_sweeps(dm)
     if args.smooth:
         out["smooth"] = bench_smooth(dm)
+    if args.foam:
+        out["foam"] = bench_foam(dm)
     if args.serve is not None:
         out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:
