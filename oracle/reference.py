@@ -296,3 +296,43 @@ def render_vjp(V, F, grid, sigma6, dL_dI, mode: int | None = None, tri_w=None):
         fac = -0.5 * xb[:, a] * xb[:, b] * (1.0 if a == b else 2.0)
         dS[i] = float(np.sum(base * fac))
     return dV, dS
+
+
+# ------------------------------------------------------- tabulated OTF
+def otf_band(otf, tau) -> np.ndarray:
+    """Band of a tabulated OTF: Re^2 + Im^2 > tau^2 in float64."""
+    otf = np.asarray(otf, dtype=np.complex128)
+    re, im = otf.real, otf.imag
+    return (re * re + im * im) > float(tau) * float(tau)
+
+
+def render_otf(V, F, grid, otf, mode: int | None = None, tri_w=None) -> np.ndarray:
+    """Image for a PSF given by its transform on the full DFT grid (an array
+    of the grid's shape, numpy fftn order; Hermitian for a real PSF), the
+    band being where |OTF| > tau, decided as Re^2 + Im^2 > tau^2 in float64:
+    I = Re(ifftn(OTF u 1_band)) / (Dx Dy Dz)."""
+    mode = grid.mode if mode is None else mode
+    otf = np.asarray(otf, dtype=np.complex128)
+    K = full_grid_k(grid)
+    xi = xi_of_k(K, grid)
+    band = otf_band(otf, grid.tau)
+    u = np.zeros(grid.n, dtype=np.complex128)
+    if band.any():
+        u[band] = mesh_transform(V, F, xi[band], grid, mode, tri_w)
+    dvol = float(grid.spacing[0]) * float(grid.spacing[1]) * float(grid.spacing[2])
+    return np.real(np.fft.ifftn(otf * u * band)) / dvol
+
+
+def render_otf_vjp(V, F, grid, otf, dL_dI, mode: int | None = None, tri_w=None) -> np.ndarray:
+    """dL/dV for the tabulated-OTF image, given dL/dI (band held fixed):
+    dL/dV = (1/(Lx Ly Lz)) sum_{k in band} Re[conj(G_k) OTF_k du_k/dV]."""
+    mode = grid.mode if mode is None else mode
+    otf = np.asarray(otf, dtype=np.complex128)
+    K = full_grid_k(grid)
+    xi = xi_of_k(K, grid)
+    band = otf_band(otf, grid.tau)
+    G = np.fft.fftn(np.asarray(dL_dI, dtype=np.float64))
+    LV = float(np.prod(lengths(grid)))
+    W = np.conj(G[band]) * otf[band] / LV
+    Vr = _d(V) - np.asarray(grid.origin, dtype=np.float64)
+    return mesh_ft_vjp_raw(Vr, F, xi[band], W, mode, tri_w) if band.any() else np.zeros((len(V), 3))
