@@ -250,6 +250,25 @@ typedef struct {
   float* dL_dsigma_dev;         /* [6] or NULL (needs dL_dimage_dev) */
 } dm_request;
 
+/* Rendering with a tabulated PSF (paper Sec. 3.2 and Sec. 7: measured or
+ * physics-based PSFs beyond the Gaussian).  otf: device complex64
+ * [n0][n1][n2/2+1], the PSF's transform at the half-spectrum DFT frequencies
+ * (the layout of a real-to-complex FFT of the PSF; it must be Hermitian,
+ * i.e. come from a real PSF, and is normalised like the Gaussian's, value 1 at
+ * xi = 0 for a unit-mass PSF).  The band is the set of positions whose value
+ * has |OTF|^2 > band_tau^2 (decided in float64); positions on the Nyquist
+ * planes of even axes use the same value for both of their aliases.  Then
+ * the image is I = Re(ifftn(OTF u 1_band)) / (Dx Dy Dz) with u the mesh
+ * transform of the grid's density mode, as in dm_render.  The band is rebuilt
+ * on every call (the table may change), which synchronises the stream once.
+ * dm_render_otf_vjp returns dL/dverts (and optionally the image) for a given
+ * dL/dimage, the band held fixed; there is no PSF gradient.  Not available
+ * through dm_batch_run or the server.  Errors as dm_render. */
+dm_status dm_render_otf(dm_handle* h, const dm_mesh* mesh, const void* otf, const dm_grid* g, float* image_out,
+                        void* stream);
+dm_status dm_render_otf_vjp(dm_handle* h, const dm_mesh* mesh, const void* otf, const dm_grid* g,
+                            const float* dL_dimage, float* dL_dverts, float* image_out, void* stream);
+
 /* Runs n independent requests of uneven sizes and grids as one batch: the
  * mesh-transform sweeps of all of them (forward, Eq. 5/7-8, and gradient,
  * Eq. 6/9-10) execute in one persistent launch whose workgroups draw work

@@ -107,6 +107,8 @@ def _load():
         "dm_topology_strips": [vp, i32, vp, vp, ctypes.POINTER(i32)],
         "dm_laplace_smooth": [vp, vp, ctypes.c_float, vp, vp, i32, ctypes.c_float, vp, vp],
         "dm_topology_set_weights": [vp, vp],
+        "dm_render_otf": [vp, ctypes.POINTER(CMesh), vp, ctypes.POINTER(CGrid), vp, vp],
+        "dm_render_otf_vjp": [vp, ctypes.POINTER(CMesh), vp, ctypes.POINTER(CGrid), vp, vp, vp, vp],
         "dm_band_size": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), ctypes.POINTER(i64), vp],
         "dm_band_export": [vp, ctypes.POINTER(CGrid), ctypes.POINTER(CPsf), vp, vp, vp, vp],
         "dm_render": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CPsf), ctypes.POINTER(CGrid), vp, vp, vp],
@@ -406,6 +408,47 @@ def render_vjp(h: Handle, verts, topo: Topology, sigma6, grid, dL_dimage, want_v
     _check(_load().dm_render_vjp(h.ptr, ctypes.byref(m), ctypes.byref(p), ctypes.byref(g), ptr(gI), ptr(dv), ptr(ds),
                                  ptr(img), ptr(sp), _stream(h.device)), "dm_render_vjp")
     return dv, ds, img
+
+
+def _otf_tensor(otf, grid):
+    torch = _torch()
+    n0, n1, n2 = (int(x) for x in grid.n)
+    if not (isinstance(otf, torch.Tensor) and otf.is_cuda and otf.dtype == torch.complex64):
+        raise TypeError("otf must be a complex64 device tensor")
+    if tuple(otf.shape) != (n0, n1, n2 // 2 + 1):
+        raise ValueError(f"otf must have shape ({n0}, {n1}, {n2 // 2 + 1}) (half spectrum)")
+    return otf.contiguous()
+
+
+def render_otf(h: Handle, verts, topo: Topology, otf, grid):
+    """Image for a tabulated PSF (dm_render_otf): ``otf`` is the complex64
+    half spectrum [n0, n1, n2 // 2 + 1] of the PSF's transform."""
+    torch = _torch()
+    verts = _dev_tensor(verts, torch.float32, 3, "verts")
+    o = _otf_tensor(otf, grid)
+    g, m = _grid(grid), _mesh(verts, topo)
+    img = torch.empty(tuple(int(x) for x in grid.n), dtype=torch.float32, device=verts.device)
+    _check(_load().dm_render_otf(h.ptr, ctypes.byref(m), ctypes.c_void_p(o.data_ptr()), ctypes.byref(g),
+                                 ctypes.c_void_p(img.data_ptr()), _stream(h.device)), "dm_render_otf")
+    return img
+
+
+def render_otf_vjp(h: Handle, verts, topo: Topology, otf, grid, dL_dimage, want_image: bool = False):
+    """(dL/dverts, image | None) for a tabulated PSF (dm_render_otf_vjp)."""
+    torch = _torch()
+    verts = _dev_tensor(verts, torch.float32, 3, "verts")
+    o = _otf_tensor(otf, grid)
+    gI = _dev_tensor(dL_dimage, torch.float32, None, "dL_dimage")
+    if tuple(gI.shape) != tuple(int(x) for x in grid.n):
+        raise ValueError("dL_dimage must have the grid's shape")
+    g, m = _grid(grid), _mesh(verts, topo)
+    dv = torch.empty_like(verts)
+    img = torch.empty(tuple(int(x) for x in grid.n), dtype=torch.float32, device=verts.device) if want_image else None
+    _check(_load().dm_render_otf_vjp(h.ptr, ctypes.byref(m), ctypes.c_void_p(o.data_ptr()), ctypes.byref(g),
+                                     ctypes.c_void_p(gI.data_ptr()), ctypes.c_void_p(dv.data_ptr()),
+                                     ctypes.c_void_p(img.data_ptr() if img is not None else 0), _stream(h.device)),
+           "dm_render_otf_vjp")
+    return dv, img
 
 
 def batch_run(h: Handle, requests, want_image: bool = True, want_verts: bool = True, want_sigma: bool = True):

@@ -115,6 +115,7 @@ struct dm_handle {
   size_t ws_bytes = 0;
   std::map<BandKey, BandEntry> bands;
   std::list<BandKey> band_lru;   // front = most recent
+  BandEntry otf_band;            // band of the last tabulated-OTF call (rebuilt every call)
   std::map<std::tuple<int, int, int>, FftPlans> ffts;
   rocfft_execution_info exec_info = nullptr;
   hipEvent_t last_ev = nullptr;
@@ -339,6 +340,50 @@ dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t 
   be.pins = pin ? 1 : 0;
   h->bands[key] = be;
   h->band_lru.push_front(key);
+  *out = be.dev;
+  return DM_OK;
+}
+
+// Band of a tabulated OTF (half spectrum, device): rebuilt on every call since
+// the table may change between calls; its memory is reused.  Synchronises s.
+dm_status get_otf_band(dm_handle* h, const dm_grid* g, const float2* otf, hipStream_t s, BandDev* out) {
+  const GridC gc = make_gridc(g);
+  const int64_t n_pos = (int64_t)gc.n0 * gc.n1 * gc.n2h;
+  const int64_t n_slots = (int64_t)((gc.n0 + 3) / 4) * ((gc.n1 + 3) / 4) * ((gc.n2h + 3) / 4) * 64;
+  const int64_t ntmp = scan_tmp_elems(n_slots);
+  Carver cv;
+  const size_t o_cnt = cv.take<int32_t>(n_slots), o_off = cv.take<int32_t>(n_slots), o_tmp = cv.take<int32_t>(ntmp),
+               o_tot = cv.take<int64_t>(1);
+  DM_TRY(ensure_ws(h, cv.off));
+  int32_t* cnt = at<int32_t>(h, o_cnt);
+  int32_t* off = at<int32_t>(h, o_off);
+  const double tau = (double)(g->band_tau > 0.0f ? g->band_tau : 0.0f);
+  HIP_TRY(launch_band_count_otf(gc, otf, tau * tau, cnt, n_slots, s));
+  HIP_TRY(launch_scan(cnt, off, n_slots, at<int32_t>(h, o_tmp), at<int64_t>(h, o_tot), s));
+  int64_t total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, at<int64_t>(h, o_tot), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  Carver bc;
+  const int64_t ne = std::max<int64_t>(total, 1);
+  const size_t o_kf = bc.take<float4>(ne), o_w = bc.take<float>(ne), o_pos = bc.take<int32_t>(ne),
+               o_map = bc.take<int32_t>(n_pos);
+  BandEntry& be = h->otf_band;
+  if (be.bytes < bc.off) {
+    dev_free(h, be.mem, be.bytes);
+    be.mem = nullptr;
+    be.bytes = 0;
+    DM_TRY(dev_alloc(h, &be.mem, bc.off));
+    be.bytes = bc.off;
+  }
+  char* base = static_cast<char*>(be.mem);
+  be.dev.n_entries = total;
+  be.dev.n_pos = n_pos;
+  be.dev.kf = reinterpret_cast<float4*>(base + o_kf);
+  be.dev.wgt = reinterpret_cast<float*>(base + o_w);
+  be.dev.pos = reinterpret_cast<int32_t*>(base + o_pos);
+  be.dev.map = reinterpret_cast<int32_t*>(base + o_map);
+  be.dev.otf = otf;
+  HIP_TRY(launch_band_fill_otf(gc, otf, tau * tau, cnt, off, n_slots, be.dev, s));
   *out = be.dev;
   return DM_OK;
 }
@@ -580,6 +625,7 @@ struct ReqPlan {
   float* dS = nullptr;
   const float* spec_in = nullptr;
   float* spec_out = nullptr;
+  const float2* otf = nullptr;   // tabulated OTF (half spectrum) instead of the Gaussian PSF
   int mode = 0, nt = 0, nv = 0, nc = 3, prep_blocks = 1, adj_blocks = 1;
   int64_t nvox = 0, nE = 0;
   bool want_vjp = false, need_spec = false, empty = false, pinned = false;
@@ -625,8 +671,13 @@ dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch) {
   P.nv = P.m->n_verts;
   P.nvox = (int64_t)P.g.n[0] * P.g.n[1] * P.g.n[2];
   P.want_vjp = P.dLdI && (P.dV || P.dS);
-  DM_TRY(get_band(h, &P.g, &P.psf, s, &P.b, batch));
-  P.pinned = batch;
+  if (P.otf) {
+    DM_TRY(get_otf_band(h, &P.g, P.otf, s, &P.b));
+    P.pinned = false;
+  } else {
+    DM_TRY(get_band(h, &P.g, &P.psf, s, &P.b, batch));
+    P.pinned = batch;
+  }
   P.nE = P.b.n_entries;
   if (P.image || P.want_vjp) DM_TRY(get_fft(h, &P.g, &P.fp));
   P.empty = P.nE == 0 || P.nt == 0;
@@ -776,12 +827,14 @@ dm_status stage_post(dm_handle* h, ReqPlan& P, hipStream_t s) {
 }
 
 dm_status render_impl(dm_handle* h, const dm_mesh* m, const dm_psf* psf, const dm_grid* g, float* image,
-                      float* spec_out, const float* dLdI, float* dV, float* dS, const float* spec_in, hipStream_t s) {
+                      float* spec_out, const float* dLdI, float* dV, float* dS, const float* spec_in, hipStream_t s,
+                      const float2* otf = nullptr) {
   DM_TRY(begin_call(h, s));
   ReqPlan P;
   P.m = m;
   P.g = *g;
-  P.psf = *psf;
+  if (psf) P.psf = *psf;
+  P.otf = otf;
   P.image = image;
   P.spec_out = spec_out;
   P.dLdI = dLdI;
@@ -923,6 +976,7 @@ dm_status dm_destroy(dm_handle* h) {
   DeviceGuard dg(h->device);
   (void)hipDeviceSynchronize();
   for (auto& kv : h->bands) (void)hipFree(kv.second.mem);
+  if (h->otf_band.mem) (void)hipFree(h->otf_band.mem);
   for (auto& kv : h->ffts) {
     if (kv.second.c2r) rocfft_plan_destroy(kv.second.c2r);
     if (kv.second.r2c) rocfft_plan_destroy(kv.second.r2c);
@@ -1274,6 +1328,33 @@ dm_status dm_render_vjp(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, co
   DeviceGuard dg(h->device);
   return render_impl(h, mesh, psf, g, image_dev, nullptr, dL_dimage_dev, dL_dverts_dev, dL_dsigma_dev,
                      spectrum_in_dev, (hipStream_t)stream);
+}
+
+dm_status dm_render_otf(dm_handle* h, const dm_mesh* mesh, const void* otf_dev, const dm_grid* g, float* image_dev,
+                        void* stream) {
+  g_err.clear();
+  if (!h) return fail(DM_ERR_ARG, "NULL handle");
+  DM_TRY(check_grid(g));
+  DM_TRY(check_mesh(mesh, g->mode));
+  if (!otf_dev) return fail(DM_ERR_ARG, "otf is NULL");
+  if (!image_dev) return fail(DM_ERR_ARG, "no output requested");
+  DeviceGuard dg(h->device);
+  return render_impl(h, mesh, nullptr, g, image_dev, nullptr, nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream,
+                     static_cast<const float2*>(otf_dev));
+}
+
+dm_status dm_render_otf_vjp(dm_handle* h, const dm_mesh* mesh, const void* otf_dev, const dm_grid* g,
+                            const float* dL_dimage_dev, float* dL_dverts_dev, float* image_dev, void* stream) {
+  g_err.clear();
+  if (!h) return fail(DM_ERR_ARG, "NULL handle");
+  DM_TRY(check_grid(g));
+  DM_TRY(check_mesh(mesh, g->mode));
+  if (!otf_dev) return fail(DM_ERR_ARG, "otf is NULL");
+  if (!dL_dimage_dev) return fail(DM_ERR_ARG, "dL_dimage is NULL");
+  if (!dL_dverts_dev && !image_dev) return fail(DM_ERR_ARG, "no output requested");
+  DeviceGuard dg(h->device);
+  return render_impl(h, mesh, nullptr, g, image_dev, nullptr, dL_dimage_dev, dL_dverts_dev, nullptr, nullptr,
+                     (hipStream_t)stream, static_cast<const float2*>(otf_dev));
 }
 
 dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* stream) {

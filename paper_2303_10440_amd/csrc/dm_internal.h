@@ -33,6 +33,9 @@ struct BandDev {
   float* wgt;              // [n_entries] alias weight (1 or 1/2)
   int32_t* pos;            // [n_entries] half-spectrum position
   int32_t* map;            // [n_pos] first entry | (count-1) << 30, or -1
+  // Tabulated OTF per half-spectrum position [n_pos] (complex), or nullptr:
+  // then the Gaussian value kf.w of each entry is the OTF.
+  const float2* otf;
 };
 
 // Triangle record for the sweeps: 16 floats (one 64-byte scalar load), for
@@ -96,6 +99,12 @@ hipError_t launch_band_count(const GridC& g, const double* sigma6, double qmax, 
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* block_tmp, int64_t* total,
                        hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
+// Band of a tabulated OTF: positions with Re^2 + Im^2 > tau2 (float64), all
+// their aliases; entries get kf.w = 1.
+hipError_t launch_band_count_otf(const GridC& g, const float2* otf, double tau2, int32_t* cnt, int64_t n_slots,
+                                 hipStream_t s);
+hipError_t launch_band_fill_otf(const GridC& g, const float2* otf, double tau2, const int32_t* cnt,
+                                const int32_t* off, int64_t n_slots, BandDev b, hipStream_t s);
 hipError_t launch_band_fill(const GridC& g, const double* sigma6, double qmax, const int32_t* cnt,
                             const int32_t* off, int64_t n_slots, BandDev b, hipStream_t s);
 

@@ -397,6 +397,52 @@ __global__ void k_band_fill(GridC g, Sig6 S, double qmax, const int32_t* __restr
   }
 }
 
+// Band of a tabulated OTF (a PSF given as an array of its transform): the
+// half-spectrum positions whose value has Re^2 + Im^2 > tau^2, decided in
+// float64 without contraction so that membership is reproducible.
+#pragma clang fp contract(off)
+__device__ __noinline__ bool otf_in_band(float2 o, double tau2) {
+  const double re = o.x, im = o.y;
+  return re * re + im * im > tau2;
+}
+#pragma clang fp contract(on)
+
+__global__ void k_band_count_otf(GridC g, const float2* __restrict__ otf, double tau2, int32_t* __restrict__ cnt,
+                                 int64_t n_slots) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= n_slots) return;
+  int ix, iy, iz;
+  int c = 0;
+  if (slot_pos(g, slot, ix, iy, iz)) {
+    const int p = (ix * g.n1 + iy) * g.n2h + iz;
+    if (otf_in_band(otf[p], tau2)) c = aliases_of(g, ix, iy, iz).n;
+  }
+  cnt[slot] = c;
+}
+
+__global__ void k_band_fill_otf(GridC g, const float2* __restrict__ otf, double tau2,
+                                const int32_t* __restrict__ cnt, const int32_t* __restrict__ off, int64_t n_slots,
+                                BandDev b) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= n_slots) return;
+  int ix, iy, iz;
+  if (!slot_pos(g, slot, ix, iy, iz)) return;
+  const int p = (ix * g.n1 + iy) * g.n2h + iz;
+  const int c = cnt[slot];
+  if (c == 0) {
+    b.map[p] = -1;
+    return;
+  }
+  const int e0 = off[slot];
+  b.map[p] = e0 | ((c - 1) << 30);
+  const Aliases a = aliases_of(g, ix, iy, iz);
+  for (int j = 0; j < a.n; ++j) {
+    b.kf[e0 + j] = make_float4((float)a.k[j][0], (float)a.k[j][1], (float)a.k[j][2], 1.0f);
+    b.wgt[e0 + j] = a.n == 2 ? 0.5f : 1.0f;
+    b.pos[e0 + j] = p;
+  }
+}
+
 // ------------------------------------------------------------- scan (int32)
 constexpr int SCAN_T = 256, SCAN_PER = 4, SCAN_BLK = SCAN_T * SCAN_PER;
 
@@ -801,9 +847,15 @@ __global__ void k_fwd_finalize(GridC g, BandDev b, const float2* __restrict__ pa
       const float4 k = b.kf[e];
       const float2 u = finish_u<MODE>(g, info, k.x, k.y, k.z, sr, si);
       if (spec_out) spec_out[e] = u;
-      const float hw = k.w * b.wgt[e];
+      const float hw = b.otf ? b.wgt[e] : k.w * b.wgt[e];
       xr = fmaf(hw, u.x, xr);
       xi = fmaf(hw, u.y, xi);
+    }
+    if (b.otf) {   // one tabulated value per position, shared by its aliases
+      const float2 o = b.otf[p];
+      const float tr = xr * o.x - xi * o.y;
+      xi = fmaf(xr, o.y, xi * o.x);
+      xr = tr;
     }
   }
   if (xhalf) xhalf[p] = make_float2(xr * g.inv_LV, xi * g.inv_LV);
@@ -817,9 +869,15 @@ __global__ void k_spec_scatter(GridC g, BandDev b, const float2* __restrict__ sp
   if (m >= 0) {
     const int e0 = m & 0x3fffffff, cntm1 = (m >> 30) & 1;
     for (int e = e0; e <= e0 + cntm1; ++e) {
-      const float hw = b.kf[e].w * b.wgt[e];
+      const float hw = b.otf ? b.wgt[e] : b.kf[e].w * b.wgt[e];
       xr = fmaf(hw, spec[e].x, xr);
       xi = fmaf(hw, spec[e].y, xi);
+    }
+    if (b.otf) {
+      const float2 o = b.otf[p];
+      const float tr = xr * o.x - xi * o.y;
+      xi = fmaf(xr, o.y, xi * o.x);
+      xr = tr;
     }
   }
   xhalf[p] = make_float2(xr * g.inv_LV, xi * g.inv_LV);
@@ -845,9 +903,16 @@ __global__ void k_adjoint(GridC g, BandDev b, const float2* __restrict__ ghat, c
     float pr, pi;
     ref_phase(info, k.x, k.y, k.z, pr, pi);
     // W = c_p w_alias h_hat conj(G) e^{-i xi.(c-o)} / (Lx Ly Lz) [/ area]
-    const float a = cp * b.wgt[e] * k.w * g.inv_LV * inv_area;
-    const float wr = a * (G.x * pr + G.y * pi);
-    const float wi = a * (G.x * pi - G.y * pr);
+    // (a tabulated OTF value multiplies as a complex number)
+    const float a = cp * b.wgt[e] * (b.otf ? 1.0f : k.w) * g.inv_LV * inv_area;
+    float wr = a * (G.x * pr + G.y * pi);
+    float wi = a * (G.x * pi - G.y * pr);
+    if (b.otf) {
+      const float2 o = b.otf[p];
+      const float tr = wr * o.x - wi * o.y;
+      wi = fmaf(wr, o.y, wi * o.x);
+      wr = tr;
+    }
     erec[ERC * e] = make_float4(k.x, k.y, k.z, wr);
     erec[ERC * e + 1] = make_float4(wi, k.x * g.two_pi_over_L[0], k.y * g.two_pi_over_L[1], k.z * g.two_pi_over_L[2]);
     erec[ERC * e + 2] = make_float4(sqrtf(fmaf(wr, wr, wi * wi)), atan2f(wi, wr) * INV_TWO_PI_F, 0.0f, 0.0f);
@@ -1408,6 +1473,19 @@ hipError_t launch_band_fill(const GridC& g, const double* sigma6, double qmax, c
   Sig6 S;
   for (int j = 0; j < 6; ++j) S.s[j] = sigma6[j];
   hipLaunchKernelGGL(k_band_fill, dim3(blocks_for(n_slots, 256)), dim3(256), 0, s, g, S, qmax, cnt, off, n_slots, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_count_otf(const GridC& g, const float2* otf, double tau2, int32_t* cnt, int64_t n_slots,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_band_count_otf, dim3(blocks_for(n_slots, 256)), dim3(256), 0, s, g, otf, tau2, cnt, n_slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_fill_otf(const GridC& g, const float2* otf, double tau2, const int32_t* cnt,
+                                const int32_t* off, int64_t n_slots, BandDev b, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_fill_otf, dim3(blocks_for(n_slots, 256)), dim3(256), 0, s, g, otf, tau2, cnt, off,
+                     n_slots, b);
   return hipGetLastError();
 }
 
