@@ -325,6 +325,38 @@ def bench_foam(dm, steps: int = 20) -> dict:
     return out
 
 
+def bench_otf(dm, case, steps: int = 20) -> dict:
+    """The single-cell workload with a tabulated PSF instead of the Gaussian:
+    an aberrated OTF table (envelope widths 0.3 / 0.9 um, a defocus-like
+    phase and a missing cone), band |OTF| > 1e-3 rebuilt on every call; one
+    dm_render_otf_vjp (image + dL/dverts) per step."""
+    import torch
+    from workloads import psfs
+    h = dm.Handle(0)
+    g = case.grid
+    otf_full = psfs.aberrated_otf(g, 0.3, 0.9, defocus=0.8, cone=1.5)
+    otf = torch.tensor(psfs.half_spectrum(otf_full), device="cuda:0")
+    topo = h.topology(case.F, n_verts=len(case.V))
+    V = torch.tensor(case.V, device="cuda:0")
+    G = torch.tensor(np.random.default_rng(0).standard_normal(g.n).astype(np.float32), device="cuda:0")
+    for _ in range(3):
+        dm.render_otf_vjp(h, V, topo, otf, g, G, want_image=True)
+    torch.cuda.synchronize()
+    s_ = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s_)
+    for _ in range(steps):
+        dm.render_otf_vjp(h, V, topo, otf, g, G, want_image=True)
+    e1.record(s_)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    re, im = otf.real.double(), otf.imag.double()
+    n_pos = int(((re * re + im * im) > float(np.float32(g.tau)) ** 2).sum().item())
+    return {"workload": "single cell, tabulated aberrated OTF (defocus phase, missing cone), fwd + gradient",
+            "ms_per_step": ms, "band_positions": n_pos, "n_triangles": int(case.F.shape[0]),
+            "pairs_per_s": n_pos * case.F.shape[0] / (ms * 1e-3)}
+
+
 def bench_smooth(dm, reps: int = 20) -> dict:
     """The shape step's Laplacian filter (I + 50 L)^{-2} g (dm_laplace_smooth)
     on the single-cell mesh (2562 vertices) and a 20252-vertex geodesic
@@ -434,6 +466,8 @@ def main() -> int:
     ap.add_argument("--batch", action="store_true", help="add the 64-cell batched vs looped comparison")
     ap.add_argument("--sweeps", action="store_true",
                     help="add the paper's mesh-transform benchmark shapes (image size, triangle count)")
+    ap.add_argument("--otf", action="store_true",
+                    help="add the single-cell workload with a tabulated (aberrated) PSF")
     ap.add_argument("--foam", action="store_true",
                     help="add the 8-cell cluster (per-face density weights) in both densities")
     ap.add_argument("--smooth", action="store_true",
@@ -562,6 +596,8 @@ def main() -> int:
         out["smooth"] = bench_smooth(dm)
     if args.foam:
         out["foam"] = bench_foam(dm)
+    if args.otf:
+        out["otf"] = bench_otf(dm, case)
     if args.serve is not None:
         out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:
