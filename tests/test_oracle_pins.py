@@ -448,3 +448,24 @@ def test_render_vjp_matches_finite_differences(ref, mode):
         Sm[i] -= h
         fd = (loss(V, tuple(Sp), tuple(Sarr)) - loss(V, tuple(Sm), tuple(Sarr))) / (2 * h)
         assert abs(dS[i] - fd) < 1e-6 * np.abs(dS).max() + 1e-14, (i, dS[i], fd)
+
+
+@pytest.mark.parametrize("mode", [VOLUME, SURFACE])
+def test_adjoint_dot_product(ref, mode):
+    """<G, J d> = <J^T G, d> for the linear map J: (dV, dSigma) -> dI, with
+    J d taken by central differences of the image along one random
+    direction of all vertices and all six covariance entries at once, and
+    J^T G the gradient render_vjp returns for dL/dI = G (band fixed)."""
+    V, F, g, S = _small_case(mode)
+    rng = np.random.default_rng(13)
+    G = rng.normal(size=g.n)
+    dVd = rng.normal(size=V.shape)
+    dSd = rng.normal(size=6) * 0.05
+    S0 = np.array(S, float)
+    h = 1e-4
+    Ip = ref.render(V + h * dVd, F, g, tuple(S0 + h * dSd), band_sigma6=tuple(S0))
+    Im = ref.render(V - h * dVd, F, g, tuple(S0 - h * dSd), band_sigma6=tuple(S0))
+    lhs = float((G * (Ip - Im)).sum() / (2 * h))
+    gV, gS = ref.render_vjp(V, F, g, tuple(S0), G)
+    rhs = float((gV * dVd).sum() + (gS * dSd).sum())
+    assert abs(lhs - rhs) < 1e-6 * max(abs(lhs), abs(rhs)), (lhs, rhs)
