@@ -629,6 +629,7 @@ struct ReqPlan {
   int mode = 0, nt = 0, nv = 0, nc = 3, prep_blocks = 1, adj_blocks = 1;
   int64_t nvox = 0, nE = 0;
   bool want_vjp = false, need_spec = false, empty = false, pinned = false;
+  bool direct = false;   // in a batch: large enough to run its own sweep launches
   GridC gc{};
   BandDev b{};
   FftPlans* fp = nullptr;
@@ -648,6 +649,13 @@ struct ReqPlan {
 // sweeps, at most 8 forward chunks so the partials of large requests stay
 // bounded (8 B x entries x 8).  Gradient items cover sub x vjp_chunk(mode) entries
 // (at most 256 chunks, as in plan_vjp) and up to VJP_TPB_MAX triangles.
+// A request of at least this many (entry, triangle) pairs fills the GPU with
+// its own sweep launches (about 1 ms each), so inside a batch it runs them
+// (the single-call plans) instead of joining the shared persistent launch.
+// The choice depends on the request alone, so its result is still the same
+// in any batch.
+constexpr double BATCH_DIRECT_PAIRS = 5e8;
+
 SweepPlan plan_fwd_batch(int64_t nE, int nt) {
   SweepPlan sp;
   (void)nE;
@@ -682,8 +690,10 @@ dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch) {
   if (P.image || P.want_vjp) DM_TRY(get_fft(h, &P.g, &P.fp));
   P.empty = P.nE == 0 || P.nt == 0;
   P.need_spec = (P.image && !P.spec_in) || (P.dS && !P.spec_in) || P.spec_out;
-  P.fsp = batch ? plan_fwd_batch(P.nE, P.nt) : plan_fwd(P.nE, P.nt);
-  P.vsp = batch ? plan_vjp_batch(P.nE, P.nt, P.g.mode) : plan_vjp(P.nE, P.nt, P.g.mode);
+  P.direct = batch && (double)P.nE * P.nt >= BATCH_DIRECT_PAIRS;
+  const bool shared = batch && !P.direct;
+  P.fsp = shared ? plan_fwd_batch(P.nE, P.nt) : plan_fwd(P.nE, P.nt);
+  P.vsp = shared ? plan_vjp_batch(P.nE, P.nt, P.g.mode) : plan_vjp(P.nE, P.nt, P.g.mode);
   P.nc = nchannels(P.mode);
   P.prep_blocks = mesh_prep_blocks(P.nt);
   P.adj_blocks = adjoint_blocks(P.gc);
@@ -758,7 +768,7 @@ dm_status stage_sweeps(dm_handle* h, ReqPlan& P, hipStream_t s) {
 
 // Work items of this request for the persistent batched sweep.
 void add_items(const ReqPlan& P, int req, std::vector<SweepItem>& items, std::vector<double>& cost) {
-  if (P.empty) return;
+  if (P.empty || P.direct) return;
   if (P.need_spec)
     for (int c = 0; c < P.fsp.n_chunks; ++c) {
       const int tris = std::min(P.nt, (c + 1) * P.fsp.per_chunk) - c * P.fsp.per_chunk;
@@ -892,7 +902,7 @@ void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
     L.off[i] = L.total;
     L.total += align_up(P[i].bytes);
     add_items(P[i], (int)i, items, cost);
-    L.pairs += (double)P[i].nE * P[i].nt;
+    if (!P[i].direct) L.pairs += (double)P[i].nE * P[i].nt;
   }
   std::vector<size_t> order(items.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
@@ -927,6 +937,8 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
     L.reqs[i] = sweep_req(P[i]);
   }
   for (size_t i = 0; i < n; ++i) DM_TRY(stage_pre(h, P[i], s));
+  for (size_t i = 0; i < n; ++i)
+    if (P[i].direct) DM_TRY(stage_sweeps(h, P[i], s));
   if (!L.items.empty()) {
     HIP_TRY(hipMemcpyAsync(base + L.o_items, L.items.data(), L.items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
                            s));

@@ -130,3 +130,26 @@ def test_batch_rejects_whole_batch_and_writes_nothing(dm, handle):
     assert st == -3
     for img, dv in outs:
         assert bool((img == 7.0).all()) and bool((dv == 7.0).all())
+
+
+def test_large_request_in_a_batch_runs_its_own_sweeps(dm, handle):
+    """A request of 2.8e9 pairs (the single cell) is large enough to run its
+    own sweep launches inside a batch: its outputs are bitwise those of the
+    single call, while a small request shares the persistent launch."""
+    import torch
+    big = configs.cfg3()
+    small = configs.cfg1()
+    tb = handle.topology(big.F, n_verts=len(big.V))
+    ts = handle.topology(small.F, n_verts=len(small.V))
+    Gb = dev(np.random.default_rng(21).standard_normal(big.grid.n).astype(np.float32))
+    Gs = dev(np.random.default_rng(22).standard_normal(small.grid.n).astype(np.float32))
+    single = dm.render_vjp(handle, dev(big.V), tb, big.sigma, big.grid, Gb, want_image=True)
+    out = dm.batch_run(handle, [(dev(small.V), ts, small.sigma, small.grid, Gs),
+                                (dev(big.V), tb, big.sigma, big.grid, Gb)])
+    alone = dm.batch_run(handle, [(dev(small.V), ts, small.sigma, small.grid, Gs)])
+    torch.cuda.synchronize()
+    img, dv, ds = out[1]
+    say("large request in batch: image equal", torch.equal(img, single[2]), "dV equal", torch.equal(dv, single[0]))
+    assert torch.equal(img, single[2]) and torch.equal(dv, single[0]) and torch.equal(ds, single[1])
+    for a, b in zip(out[0], alone[0]):
+        assert torch.equal(a, b)
