@@ -227,6 +227,144 @@ __global__ void __launch_bounds__(CG_T) k_laplace_smooth(int nv, const int32_t* 
   }
 }
 
+// Resident variant for meshes of at most CG_T * CG_VPT_MAX vertices whose degrees
+// fit the neighbour table: thread t owns vertices t + k CG_T (k < VPT) and
+// keeps their x, r, 1/d and neighbour lists in registers; only p, which the
+// Laplacian product reads at the neighbours, lives in LDS.  An iteration
+// then makes no global-memory round trip.  Same algorithm, same stopping
+// rule and float64 reductions as cg_solve.
+constexpr int CG_VPT_MAX = 3;   // 4 would exceed the 128 VGPRs of a 1024-lane workgroup
+
+template <int VPT>
+__device__ int cg_solve_res(int nv, const int (&nb)[VPT][ADJ_W], const float (&dinv)[VPT], const float (&d)[VPT],
+                            float lam, float (&x)[VPT][3], const float (&b)[VPT][3], float (*p_lds)[3], int max_iter,
+                            float tol, float* res, CgLds& L) {
+  float r[VPT][3];
+  double bz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int i = threadIdx.x + k * CG_T;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[k][c] = b[k][c];
+      x[k][c] = 0.0f;
+      if (i < nv) {
+        p_lds[i][c] = b[k][c] * dinv[k];
+        bz[c] += (double)b[k][c] * b[k][c];
+        bz[3 + c] += (double)b[k][c] * (b[k][c] * dinv[k]);
+      }
+    }
+  }
+  block_sum<6>(bz, L);   // its barriers also publish p
+  const double bb[3] = {bz[0], bz[1], bz[2]};
+  double rz[3] = {bz[3], bz[4], bz[5]}, rr[3] = {bz[0], bz[1], bz[2]};
+  const double tol2 = (double)tol * tol;
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    if (rr[0] <= tol2 * bb[0] && rr[1] <= tol2 * bb[1] && rr[2] <= tol2 * bb[2]) break;
+    float q[VPT][3], pk[VPT][3];
+    double pq[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * CG_T;
+      float s3[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < ADJ_W; ++j)
+        if (nb[k][j] >= 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) s3[c] += p_lds[nb[k][j]][c];
+        }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pk[k][c] = i < nv ? p_lds[i][c] : 0.0f;
+        q[k][c] = fmaf(d[k], pk[k][c], -lam * s3[c]);
+        pq[c] += (double)pk[k][c] * q[k][c];
+      }
+    }
+    block_sum<3>(pq, L);
+    float alpha[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) alpha[c] = pq[c] > 0.0 ? (float)(rz[c] / pq[c]) : 0.0f;
+    double rn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x[k][c] = fmaf(alpha[c], pk[k][c], x[k][c]);
+        r[k][c] = fmaf(-alpha[c], q[k][c], r[k][c]);
+        rn[c] += (double)r[k][c] * r[k][c];
+        rn[3 + c] += (double)r[k][c] * (r[k][c] * dinv[k]);
+      }
+    block_sum<6>(rn, L);   // all reads of p for this iteration are done
+    float beta[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      beta[c] = rz[c] > 0.0 ? (float)(rn[3 + c] / rz[c]) : 0.0f;
+      rz[c] = rn[3 + c];
+      rr[c] = rn[c];
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * CG_T;
+      if (i < nv)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p_lds[i][c] = fmaf(beta[c], pk[k][c], r[k][c] * dinv[k]);
+    }
+    __syncthreads();
+  }
+  double worst = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (bb[c] > 0.0) worst = fmax(worst, sqrt(rr[c] / bb[c]));
+  *res = (float)worst;
+  return it;
+}
+
+template <int VPT>
+__global__ void __launch_bounds__(CG_T) k_laplace_smooth_res(int nv, const int32_t* __restrict__ tab, float lam,
+                                                              const float* g, float* out, int max_iter, float tol,
+                                                              float* __restrict__ info) {
+  __shared__ CgLds L;
+  __shared__ float p_lds[CG_T * VPT][3];
+  int nb[VPT][ADJ_W];
+  float dinv[VPT], d[VPT], b[VPT][3], x[VPT][3];
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int i = threadIdx.x + k * CG_T;
+    int deg = 0;
+#pragma unroll
+    for (int j = 0; j < ADJ_W; ++j) {
+      nb[k][j] = i < nv ? tab[(size_t)i * ADJ_W + j] : -1;
+      deg += nb[k][j] >= 0 ? 1 : 0;
+    }
+    d[k] = fmaf(lam, (float)deg, 1.0f);
+    dinv[k] = 1.0f / d[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[k][c] = i < nv ? g[3 * i + c] : 0.0f;
+  }
+  float res1 = 0.0f, res2 = 0.0f;
+  const int it1 = cg_solve_res<VPT>(nv, nb, dinv, d, lam, x, b, p_lds, max_iter, tol, &res1, L);
+#pragma unroll
+  for (int k = 0; k < VPT; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[k][c] = x[k][c];
+  __syncthreads();
+  const int it2 = cg_solve_res<VPT>(nv, nb, dinv, d, lam, x, b, p_lds, max_iter, tol, &res2, L);
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int i = threadIdx.x + k * CG_T;
+    if (i < nv)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[3 * i + c] = x[k][c];
+  }
+  if (info != nullptr && threadIdx.x == 0) {
+    info[0] = (float)it1;
+    info[1] = res1;
+    info[2] = (float)it2;
+    info[3] = res2;
+  }
+}
+
 }  // namespace
 
 size_t laplace_smooth_workspace(int nv) { return sizeof(float) * 13 * (size_t)nv; }
@@ -234,7 +372,18 @@ size_t laplace_smooth_workspace(int nv) { return sizeof(float) * 13 * (size_t)nv
 hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, const int32_t* adj_tab,
                                  float lam, const float* g, float* out, float* ws, int max_iter, float tol,
                                  float* info, hipStream_t s) {
-  if (adj_tab != nullptr)
+  if (adj_tab != nullptr && nv <= CG_T * CG_VPT_MAX) {
+    const int vpt = (nv + CG_T - 1) / CG_T;
+    if (vpt <= 1)
+      hipLaunchKernelGGL(k_laplace_smooth_res<1>, dim3(1), dim3(CG_T), 0, s, nv, adj_tab, lam, g, out, max_iter, tol,
+                         info);
+    else if (vpt == 2)
+      hipLaunchKernelGGL(k_laplace_smooth_res<2>, dim3(1), dim3(CG_T), 0, s, nv, adj_tab, lam, g, out, max_iter, tol,
+                         info);
+    else
+      hipLaunchKernelGGL(k_laplace_smooth_res<3>, dim3(1), dim3(CG_T), 0, s, nv, adj_tab, lam, g, out, max_iter, tol,
+                         info);
+  } else if (adj_tab != nullptr)
     hipLaunchKernelGGL(k_laplace_smooth<true>, dim3(1), dim3(CG_T), 0, s, nv, adj_off, adj_nbr, adj_tab, lam, g, out,
                        ws, max_iter, tol, info);
   else
