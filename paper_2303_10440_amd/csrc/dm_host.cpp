@@ -929,16 +929,24 @@ void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
   L.total += 256;
 }
 
-dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s) {
+// Enqueues a planned batch on s: every request's pre-steps, the shared
+// persistent launch and the post-steps of the requests in it, then each large
+// request's own sweeps and post-steps.  With req_done, an event is recorded
+// after each request's last step (req_done[i] for request i), so that a
+// caller can hand out results as they complete.
+dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s,
+                        const std::vector<hipEvent_t>* req_done = nullptr) {
   const size_t n = P.size();
   L.reqs.resize(n);
   for (size_t i = 0; i < n; ++i) {
     P[i].base = base + L.off[i];
     L.reqs[i] = sweep_req(P[i]);
   }
+  auto done = [&](size_t i) -> dm_status {
+    if (req_done && (*req_done)[i]) HIP_TRY(hipEventRecord((*req_done)[i], s));
+    return DM_OK;
+  };
   for (size_t i = 0; i < n; ++i) DM_TRY(stage_pre(h, P[i], s));
-  for (size_t i = 0; i < n; ++i)
-    if (P[i].direct) DM_TRY(stage_sweeps(h, P[i], s));
   if (!L.items.empty()) {
     HIP_TRY(hipMemcpyAsync(base + L.o_items, L.items.data(), L.items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
                            s));
@@ -949,7 +957,17 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
                                reinterpret_cast<int*>(base + L.o_counter), s));
     tm.done();
   }
-  for (size_t i = 0; i < n; ++i) DM_TRY(stage_post(h, P[i], s));
+  for (size_t i = 0; i < n; ++i)
+    if (!P[i].direct) {
+      DM_TRY(stage_post(h, P[i], s));
+      DM_TRY(done(i));
+    }
+  for (size_t i = 0; i < n; ++i)
+    if (P[i].direct) {
+      DM_TRY(stage_sweeps(h, P[i], s));
+      DM_TRY(stage_post(h, P[i], s));
+      DM_TRY(done(i));
+    }
   return DM_OK;
 }
 
@@ -1465,7 +1483,9 @@ struct ServeReq {
 
 struct Inflight {
   std::vector<uint64_t> tickets;
-  hipEvent_t ev = nullptr;
+  std::vector<hipEvent_t> req_ev;   // per ticket: its outputs are complete
+  std::vector<char> finished;       // per ticket: already handed out
+  hipEvent_t ev = nullptr;          // the whole batch (slot and memory free)
   size_t bytes = 0;
   int slot = 0;
   void* mem = nullptr;    // fallback allocation when the stream-ordered pool is unavailable
@@ -1511,20 +1531,31 @@ void finish_locked(dm_server* S, uint64_t t, dm_status st, int32_t batch) {
     S->stats.rejected++;
 }
 
-// Retires finished batches (mu held).
+// Hands out finished requests and retires finished batches (mu held).
 void retire_locked(dm_server* S) {
   bool any = false;
   for (size_t i = 0; i < S->inflight.size();) {
     Inflight& b = S->inflight[i];
+    for (size_t k = 0; k < b.tickets.size(); ++k) {
+      if (b.finished[k] || !b.req_ev[k]) continue;
+      const hipError_t qk = hipEventQuery(b.req_ev[k]);
+      if (qk == hipErrorNotReady) continue;
+      finish_locked(S, b.tickets[k], qk == hipSuccess ? DM_OK : DM_ERR_DEVICE, (int32_t)b.tickets.size());
+      b.finished[k] = 1;
+      any = true;
+    }
     const hipError_t q = hipEventQuery(b.ev);
     if (q == hipErrorNotReady) {
       ++i;
       continue;
     }
     const dm_status st = q == hipSuccess ? DM_OK : DM_ERR_DEVICE;
-    for (uint64_t t : b.tickets) finish_locked(S, t, st, (int32_t)b.tickets.size());
+    for (size_t k = 0; k < b.tickets.size(); ++k)
+      if (!b.finished[k]) finish_locked(S, b.tickets[k], st, (int32_t)b.tickets.size());
     if (b.mem) (void)hipFree(b.mem);
     S->event_pool.push_back(b.ev);
+    for (hipEvent_t e : b.req_ev)
+      if (e) S->event_pool.push_back(e);
     S->busy[b.slot] = false;
     S->inflight_bytes -= std::min(S->inflight_bytes, b.bytes);
     S->inflight.erase(S->inflight.begin() + (long)i);
@@ -1590,10 +1621,26 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
     BatchLayout L;
     layout_batch(P, L);
     b.bytes = L.total;
+    // one completion event per request (events come from the server's pool)
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      b.req_ev.assign(P.size(), nullptr);
+      for (size_t i = 0; i < P.size(); ++i) {
+        if (S->event_pool.empty()) {
+          hipEvent_t ev;
+          if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) S->event_pool.push_back(ev);
+        }
+        if (!S->event_pool.empty()) {
+          b.req_ev[i] = S->event_pool.back();
+          S->event_pool.pop_back();
+        }
+      }
+      b.finished.assign(P.size(), 0);
+    }
     void* mem = nullptr;
     hipError_t e = S->pools ? hipMallocAsync(&mem, L.total, s) : hipMalloc(&mem, L.total);
     if (e != hipSuccess) st = fail(DM_ERR_DEVICE, "workspace allocation: %s", hipGetErrorString(e));
-    if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(mem), s);
+    if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(mem), s, &b.req_ev);
     if (S->pools && mem) (void)hipFreeAsync(mem, s);
     if (!S->pools) b.mem = mem;
     if (S->event_pool.empty()) {
@@ -1619,6 +1666,8 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
       S->stats.batches++;
     } else {
       if (b.ev) S->event_pool.push_back(b.ev);
+      for (hipEvent_t ev : b.req_ev)
+        if (ev) S->event_pool.push_back(ev);
       if (b.mem) (void)hipFree(b.mem);
       for (uint64_t id : ids) finish_locked(S, id, st == DM_OK ? DM_ERR_DEVICE : st, (int32_t)ids.size());
     }
