@@ -121,24 +121,24 @@ __device__ __forceinline__ Recips recips(float S, float x1, float x2) {
 }
 
 // acc += w f_T, f_T = DD3[exp](-2 pi i (t1 + {0, d2, d3})).
-//   spread < 1 rad: series about the node mean;
-//   otherwise (sorted nodes):  f = (i/S) [sinc(pi g2) e^{-2 pi i m_mh} - sinc(pi g1) e^{-2 pi i m_lm}]
+//   dd3_acc_series, for a spread below 1 rad: series about the node mean;
+//   dd3_acc_sorted, otherwise (sorted nodes):  f = (i/S) [sinc(pi g2) e^{-2 pi i m_mh} - sinc(pi g1) e^{-2 pi i m_lm}]
 //   with m_lm, m_mh the phases at the midpoints of the lo-mid and mid-hi edges.
-__device__ __forceinline__ void dd3_acc(float t1, float d2, float d3, float w, float& ar, float& ai) {
+__device__ __forceinline__ void dd3_acc_series(float t1, float d2, float d3, float w, float& ar, float& ai) {
+  const float m = (d2 + d3) * (1.0f / 3.0f);
+  const float a0 = -TWO_PI_F * m, a1 = TWO_PI_F * (d2 - m), a2 = TWO_PI_F * (d3 - m);
+  float pre, pim;
+  series_phi(fmaf(a0, a1 + a2, a1 * a2), a0 * a1 * a2, pre, pim);
+  const float r = wrap(t1 + m);
+  const float c = __builtin_amdgcn_cosf(r), sn = -__builtin_amdgcn_sinf(r);
+  ar = fmaf(w, c * pre - sn * pim, ar);
+  ai = fmaf(w, fmaf(c, pim, sn * pre), ai);
+}
+
+__device__ __forceinline__ void dd3_acc_sorted(float t1, float d2, float d3, float w, float& ar, float& ai) {
   const float lo = fminf(fminf(0.0f, d2), d3);
   const float hi = fmaxf(fmaxf(0.0f, d2), d3);
   const float s = hi - lo;
-  if (s < SERIES_REV) {
-    const float m = (d2 + d3) * (1.0f / 3.0f);
-    const float a0 = -TWO_PI_F * m, a1 = TWO_PI_F * (d2 - m), a2 = TWO_PI_F * (d3 - m);
-    float pre, pim;
-    series_phi(fmaf(a0, a1 + a2, a1 * a2), a0 * a1 * a2, pre, pim);
-    const float r = wrap(t1 + m);
-    const float c = __builtin_amdgcn_cosf(r), sn = -__builtin_amdgcn_sinf(r);
-    ar = fmaf(w, c * pre - sn * pim, ar);
-    ai = fmaf(w, fmaf(c, pim, sn * pre), ai);
-    return;
-  }
   const float mid = __builtin_amdgcn_fmed3f(0.0f, d2, d3);
   const float g1 = mid - lo, g2 = hi - mid;
   const float x1 = PI_F * g1, x2 = PI_F * g2;
@@ -156,6 +156,15 @@ __device__ __forceinline__ void dd3_acc(float t1, float d2, float d3, float w, f
   ai = fmaf(c, br, ai);
 }
 
+// Either scheme, chosen per pair by the spread.
+__device__ __forceinline__ void dd3_acc(float t1, float d2, float d3, float w, float& ar, float& ai) {
+  const float s = fmaxf(fmaxf(0.0f, d2), d3) - fminf(fminf(0.0f, d2), d3);
+  if (s < SERIES_REV)
+    dd3_acc_series(t1, d2, d3, w, ar, ai);
+  else
+    dd3_acc_sorted(t1, d2, d3, w, ar, ai);
+}
+
 // One pair of the gradient sweep: with W the adjoint weight of the frequency,
 //   VOLUME:  z[p]  = Re(W DD4_p)            (p over the slots {node 0, d2, d3})
 //   SURFACE: wf    = Re(W f_T), z[p] = Im(W DD4_p)
@@ -165,12 +174,13 @@ __device__ __forceinline__ void dd3_acc(float t1, float d2, float d3, float w, f
 //   f      = R (P_mid phi1(G2) - P_lo phi1(G1))
 //   DD4_lo = R (f - P_lo phi2(G1)),  DD4_hi = R (P_hi conj phi2(G2) - f),
 //   DD4_mid = R P_mid (phi2(G2) - conj phi2(G1)).
+// Spread below one radian: the series about the node mean (vjp_pair_series);
+// otherwise the sorted scheme (vjp_pair_sorted).  The gradient sweep queues
+// the two kinds of pairs apart, so each pass runs one scheme only.
 template <int MODE>
-__device__ __forceinline__ void vjp_pair(float t1, float d2, float d3, float wr, float wi, float& wf, float z[3]) {
-  const float lo = fminf(fminf(0.0f, d2), d3);
-  const float hi = fmaxf(fmaxf(0.0f, d2), d3);
-  const float s = hi - lo;
-  if (s < SERIES_REV) {
+__device__ __forceinline__ void vjp_pair_series(float t1, float d2, float d3, float wr, float wi, float& wf,
+                                                float z[3]) {
+  {
     const float m = (d2 + d3) * (1.0f / 3.0f);
     const float a[3] = {-TWO_PI_F * m, TWO_PI_F * (d2 - m), TWO_PI_F * (d3 - m)};
     const float E2 = fmaf(a[0], a[1] + a[2], a[1] * a[2]);
@@ -196,8 +206,15 @@ __device__ __forceinline__ void vjp_pair(float t1, float d2, float d3, float wr,
       const float Ai = fmaf(a[p], p2r, third_im) - b * p3i;
       z[p] = MODE == 0 ? gr * Ar - gi * Ai : fmaf(gr, Ai, gi * Ar);
     }
-    return;
   }
+}
+
+template <int MODE>
+__device__ __forceinline__ void vjp_pair_sorted(float t1, float d2, float d3, float wr, float wi, float& wf,
+                                                float z[3]) {
+  const float lo = fminf(fminf(0.0f, d2), d3);
+  const float hi = fmaxf(fmaxf(0.0f, d2), d3);
+  const float s = hi - lo;
   const float mid = __builtin_amdgcn_fmed3f(0.0f, d2, d3);
   const float g1 = mid - lo, g2 = hi - mid;
   const float x1 = PI_F * g1, x2 = PI_F * g2;
@@ -641,9 +658,13 @@ constexpr int FWD_TQ = 4;   // triangles whose queued pairs share one pass
 // Queued pairs of FWD_TQ consecutive triangles share one pass.  Within a pass
 // the sums are added to the per-entry LDS row triangle by triangle (a
 // triangle queues each entry at most once), so no two lanes add to the same
-// slot at once and the order of the additions is fixed.
+// slot at once and the order of the additions is fixed.  Volume mode keeps two
+// queues per wave, 0 for the series (spread below one radian) and 1 for the
+// sorted scheme, flushed in that order, so a pass runs one scheme only; in
+// surface mode queue 0 takes every pair and each lane picks its scheme (one
+// queue measured faster there).
 struct FwdLds {
-  uint16_t queue[4][FWD_TQ * 64 * FWD_J];
+  uint16_t queue[4][2][FWD_TQ * 64 * FWD_J];
   float2 fb[4][FWD_J][64];
 };
 
@@ -654,10 +675,10 @@ struct FwdLds {
 // the triangle's tag (its offset in the group sharing a pass).
 template <int MODE>
 __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int tag, const float (&kx)[FWD_J],
-                                              const float (&ky)[FWD_J], const float (&kz)[FWD_J], uint32_t vm,
+                                              const float (&ky)[FWD_J], const float (&kz)[FWD_J], int rem,
                                               float (&Xr)[FWD_J], float (&Xi)[FWD_J], float (&Yr)[FWD_J],
                                               float (&Yi)[FWD_J], float (&ar)[FWD_J], float (&ai)[FWD_J], int lane,
-                                              uint16_t* queue, int& nq) {
+                                              uint16_t (*queue)[FWD_TQ * 64 * FWD_J], int (&nq)[2]) {
   if (start) {
 #pragma unroll
     for (int j = 0; j < FWD_J; ++j) {
@@ -681,7 +702,8 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
-    const bool fast = mn >= FWD_LAG_GAP && mx >= SERIES_REV;
+    const bool close = mn < FWD_LAG_GAP, small = mx < SERIES_REV;
+    const bool fast = !close && !small;
     // the volume weight k.n carries the 1 / (4 pi^2) of the record's normal
     const float wt = MODE == 0 ? fmaf(kz[j], r[14], fmaf(ky[j], r[13], kx[j] * r[12])) : r[12] * INV_4PI2_F;
     const float kk = fast ? wt * __builtin_amdgcn_rcpf(a * b * c) : 0.0f;
@@ -689,14 +711,29 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
     const float ti = fmaf(-c, Xi[j], fmaf(b, Yi[j], -a * Ni));
     ar[j] = fmaf(kk, tr, ar[j]);
     ai[j] = fmaf(kk, ti, ai[j]);
-    const bool need = !fast && ((vm >> j) & 1u);
-    const uint64_t bal = __ballot(need);
-    if (need) {
-      const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      queue[pos] = (uint16_t)((tag << 9) | (j << 6) | lane);
+    // the lanes holding entries are the first cnt of the wave (cnt wave-uniform)
+    const int cnt = rem - 64 * j;
+    const bool valid = lane < cnt;
+    const uint64_t vmask = cnt >= 64 ? ~0ull : (cnt <= 0 ? 0ull : (1ull << cnt) - 1ull);
+    const uint64_t bs = __builtin_amdgcn_ballot_w64(MODE == 0 ? small : !fast) & vmask;
+    const uint64_t bc = MODE == 0 ? __builtin_amdgcn_ballot_w64(close) & vmask & ~bs : 0ull;
+    const uint16_t item = (uint16_t)((tag << 9) | (j << 6) | lane);
+    if (bs) {
+      if ((MODE == 0 ? small : !fast) && valid) {
+        const int pos = nq[0] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bs >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bs, 0u));
+        queue[0][pos] = item;
+      }
+      nq[0] += __popcll(bs);
     }
-    nq += __popcll(bal);
+    if (MODE == 0 && bc) {
+      if (close && !small && valid) {
+        const int pos = nq[1] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bc >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bc, 0u));
+        queue[1][pos] = item;
+      }
+      nq[1] += __popcll(bc);
+    }
     Xr[j] = Nr;
     Xi[j] = Ni;
   }
@@ -708,9 +745,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stable scheme for the queued pairs of the triangles starting at r (tag p =
-// triangle r + p TRI_REC).
-template <int MODE>
+// Stable scheme (KIND 0 series, 1 sorted, 2 either) for the pairs of queue
+// Q of the triangles starting at r (tag p = triangle r + p TRI_REC).
+template <int MODE, int Q, int KIND>
 __device__ __forceinline__ void fwd_lanes_flush(const float* r, const float4* __restrict__ kf, int64_t ew, int lane,
                                                 int w, int nq, FwdLds& L) {
   wave_lds_sync();
@@ -719,7 +756,7 @@ __device__ __forceinline__ void fwd_lanes_flush(const float* r, const float4* __
     int p = -1, jj = 0, ll = 0;
     float fr = 0.0f, fi = 0.0f;
     if (act) {
-      const int it = L.queue[w][q0 + lane];
+      const int it = L.queue[w][Q][q0 + lane];
       p = it >> 9;
       jj = (it >> 6) & 7;
       ll = it & 63;
@@ -728,7 +765,12 @@ __device__ __forceinline__ void fwd_lanes_flush(const float* r, const float4* __
       float t1, d2, d3;
       tri_phases(k.x, k.y, k.z, rp, t1, d2, d3);
       const float wt = MODE == 0 ? fmaf(k.z, rp[14], fmaf(k.y, rp[13], k.x * rp[12])) * FOUR_PI2_F : rp[12];
-      dd3_acc(t1, d2, d3, wt, fr, fi);
+      if (KIND == 0)
+        dd3_acc_series(t1, d2, d3, wt, fr, fi);
+      else if (KIND == 1)
+        dd3_acc_sorted(t1, d2, d3, wt, fr, fi);
+      else
+        dd3_acc(t1, d2, d3, wt, fr, fi);
     }
 #pragma unroll
     for (int q = 0; q < FWD_TQ; ++q) {
@@ -749,7 +791,8 @@ __device__ __forceinline__ void fwd_lanes_tile(const float4* __restrict__ kf, in
   const int64_t ew = e_chunk + (int64_t)w * 64 * FWD_J;
   float kx[FWD_J], ky[FWD_J], kz[FWD_J], ar[FWD_J], ai[FWD_J];
   float Xr[FWD_J], Xi[FWD_J], Yr[FWD_J], Yi[FWD_J];
-  uint32_t vm = 0;
+  // entries held by this wave: the first rem of its 64 FWD_J (wave-uniform)
+  const int rem = __builtin_amdgcn_readfirstlane((int)max<int64_t>(0, min<int64_t>(nE - ew, 64 * FWD_J)));
 #pragma unroll
   for (int j = 0; j < FWD_J; ++j) {
     const int64_t e = ew + 64 * j + lane;
@@ -760,25 +803,29 @@ __device__ __forceinline__ void fwd_lanes_tile(const float4* __restrict__ kf, in
       kx[j] = k.x;
       ky[j] = k.y;
       kz[j] = k.z;
-      vm |= 1u << j;
     }
     L.fb[w][j][lane] = make_float2(0.0f, 0.0f);
   }
   for (int t = t0; t < t1; t += FWD_TQ) {
     const float* r = rec + (size_t)t * TRI_REC;
-    int nq = 0;
+    int nq[2] = {0, 0};
     // triangles t, t+1, ... alternate the roles of X and Y (see fwd_lanes_tri)
-    fwd_lanes_tri<MODE>(r, t == t0 || r[15] != 0.0f, 0, kx, ky, kz, vm, Xr, Xi, Yr, Yi, ar, ai, lane, L.queue[w], nq);
+    fwd_lanes_tri<MODE>(r, t == t0 || r[15] != 0.0f, 0, kx, ky, kz, rem, Xr, Xi, Yr, Yi, ar, ai, lane, L.queue[w], nq);
     if (t + 1 < t1)
-      fwd_lanes_tri<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, 1, kx, ky, kz, vm, Yr, Yi, Xr, Xi, ar, ai, lane,
+      fwd_lanes_tri<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, 1, kx, ky, kz, rem, Yr, Yi, Xr, Xi, ar, ai, lane,
                           L.queue[w], nq);
     if (t + 2 < t1)
-      fwd_lanes_tri<MODE>(r + 2 * TRI_REC, r[2 * TRI_REC + 15] != 0.0f, 2, kx, ky, kz, vm, Xr, Xi, Yr, Yi, ar, ai,
+      fwd_lanes_tri<MODE>(r + 2 * TRI_REC, r[2 * TRI_REC + 15] != 0.0f, 2, kx, ky, kz, rem, Xr, Xi, Yr, Yi, ar, ai,
                           lane, L.queue[w], nq);
     if (t + 3 < t1)
-      fwd_lanes_tri<MODE>(r + 3 * TRI_REC, r[3 * TRI_REC + 15] != 0.0f, 3, kx, ky, kz, vm, Yr, Yi, Xr, Xi, ar, ai,
+      fwd_lanes_tri<MODE>(r + 3 * TRI_REC, r[3 * TRI_REC + 15] != 0.0f, 3, kx, ky, kz, rem, Yr, Yi, Xr, Xi, ar, ai,
                           lane, L.queue[w], nq);
-    fwd_lanes_flush<MODE>(r, kf, ew, lane, w, nq, L);
+    if (MODE == 0) {
+      fwd_lanes_flush<MODE, 0, 0>(r, kf, ew, lane, w, nq[0], L);
+      fwd_lanes_flush<MODE, 1, 1>(r, kf, ew, lane, w, nq[1], L);
+    } else {
+      fwd_lanes_flush<MODE, 0, 2>(r, kf, ew, lane, w, nq[0], L);
+    }
   }
 #pragma unroll
   for (int j = 0; j < FWD_J; ++j) {
@@ -791,7 +838,7 @@ __device__ __forceinline__ void fwd_lanes_tile(const float4* __restrict__ kf, in
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_fwd_lanes(const float4* __restrict__ kf, int64_t nE,
+__global__ void __launch_bounds__(SWEEP_T, 7) k_fwd_lanes(const float4* __restrict__ kf, int64_t nE,
                                                          const float* __restrict__ rec, int nt, int tpc,
                                                          float2* __restrict__ part) {
   __shared__ FwdLds L;
@@ -999,12 +1046,26 @@ __device__ __forceinline__ float wave_sum(float v) {
 // then over the entry chunks, each in a fixed order, into part_out[NC][nt].
 constexpr int VJP_TB = 32;   // triangles between block-level merges
 
-constexpr int VJP_RING = 1024;   // queued pairs per wave (power of two)
+// Queued pairs per wave and ring (power of two): at most 63 left from earlier
+// triangles plus 64 J from the current one.
+template <int MODE>
+constexpr int vjp_ring() {
+  return 64 + 64 * vjp_j(MODE) <= 512 ? 512 : 1024;
+}
+static_assert(64 + 64 * VJP_J_MAX <= 1024, "ring too small");
 
+// Two rings per wave: ring 0 holds pairs for the series (node spread below
+// one radian), ring 1 pairs for the sorted scheme.
+template <int MODE>
 struct VjpLds {
-  uint16_t queue[4][VJP_RING];
+  uint16_t queue[4][2][vjp_ring<MODE>()];
   float tot[4][VJP_TB][10];
   float sum[VJP_TPB_MAX][10];
+};
+
+// Head, tail and end of the previous triangle's pairs in one ring.
+struct VjpRing {
+  int head, tail, prev_end;
 };
 
 // Closed-form gradient pair from the phase factors of the three nodes with
@@ -1044,10 +1105,10 @@ template <int MODE>
 __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int tag, const float (&kx)[vjp_j(MODE)],
                                                const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
                                                const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
-                                               uint32_t vm, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
+                                               int rem, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
                                                float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)], float tpx,
-                                               float tpy, float tpz, int lane, uint16_t* ring, int& tail,
-                                               float (&acc)[MODE == 0 ? 3 : 10]) {
+                                               float tpy, float tpz, int lane, uint16_t (*ring)[vjp_ring<MODE>()],
+                                               VjpRing (&rq)[2], float (&acc)[MODE == 0 ? 3 : 10]) {
   constexpr int J = vjp_j(MODE);
   float rvg[12];
   if (MODE == 0) {
@@ -1077,7 +1138,8 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
-    const bool fast = mn >= LAG_GAP && mx >= SERIES_REV;
+    const bool close = mn < LAG_GAP, small = mx < SERIES_REV;
+    const bool fast = !close && !small;
     float wf = 0.0f, z[3];
     lag_pair_g<MODE>(a, b, fast, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z);
     if (MODE == 0) {
@@ -1094,23 +1156,39 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
         acc[3 + 3 * p] = fmaf(zp, x2, acc[3 + 3 * p]);
       }
     }
-    const bool need = !fast && ((vm >> j) & 1u);
-    const uint64_t bal = __ballot(need);
-    if (need) {
-      const int pos = tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-      ring[pos & (VJP_RING - 1)] = (uint16_t)((tag << 9) | (j << 6) | lane);
+    // Ballots of plain compares are the compares' own lane masks; the lanes
+    // holding entries are the first cnt of the wave (cnt wave-uniform).
+    const int cnt = rem - 64 * j;
+    const bool valid = lane < cnt;
+    const uint64_t vmask = cnt >= 64 ? ~0ull : (cnt <= 0 ? 0ull : (1ull << cnt) - 1ull);
+    const uint64_t bs = __builtin_amdgcn_ballot_w64(small) & vmask;
+    const uint64_t bc = __builtin_amdgcn_ballot_w64(close) & vmask & ~bs;
+    const uint16_t item = (uint16_t)((tag << 9) | (j << 6) | lane);
+    if (bs) {
+      if (small && valid) {
+        const int pos = rq[0].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bs >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bs, 0u));
+        ring[0][pos & (vjp_ring<MODE>() - 1)] = item;
+      }
+      rq[0].tail += __popcll(bs);
     }
-    tail += __popcll(bal);
+    if (bc) {
+      if (close && !small && valid) {
+        const int pos = rq[1].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bc >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bc, 0u));
+        ring[1][pos & (vjp_ring<MODE>() - 1)] = item;
+      }
+      rq[1].tail += __popcll(bc);
+    }
     Xr[j] = Nr;
     Xi[j] = Ni;
   }
 }
 
-// Stable scheme for n queued pairs from ring position head, on full waves:
-// pairs tagged cur_tag belong to triangle r_cur (sums into acc_cur), the others
-// to the previous triangle r_prev (acc_prev).
-template <int MODE>
+// Stable scheme (KIND 0 series, 1 sorted) for n queued pairs from ring
+// position head, on full waves: pairs tagged cur_tag belong to triangle r_cur
+// (sums into acc_cur), the others to the previous triangle r_prev (acc_prev).
+template <int MODE, int KIND>
 __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, int n, const float* r_cur,
                                                const float* r_prev, int cur_tag, const float4* __restrict__ erec,
                                                int64_t ew, int lane, float (&acc_cur)[MODE == 0 ? 3 : 10],
@@ -1118,14 +1196,17 @@ __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, i
   constexpr int NC = MODE == 0 ? 3 : 10;
   wave_lds_sync();
   if (lane < n) {
-    const int it = ring[(head + lane) & (VJP_RING - 1)];
+    const int it = ring[(head + lane) & (vjp_ring<MODE>() - 1)];
     const bool cur = (it >> 9) == cur_tag;
     const float* r = cur ? r_cur : r_prev;
     const int64_t e = ew + 64 * ((it >> 6) & 7) + (it & 63);
     const float4 A = erec[ERC * e], B = erec[ERC * e + 1];
     float tv, a, b, wf = 0.0f, z[3];
     tri_phases(A.x, A.y, A.z, r, tv, a, b);
-    vjp_pair<MODE>(tv, a, b, A.w, B.x, wf, z);
+    if (KIND == 0)
+      vjp_pair_series<MODE>(tv, a, b, A.w, B.x, wf, z);
+    else
+      vjp_pair_sorted<MODE>(tv, a, b, A.w, B.x, wf, z);
     float add[NC];
     if (MODE == 0) {
 #pragma unroll
@@ -1150,7 +1231,7 @@ __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, i
 // Wave sums of one triangle into L.tot[w][tt].
 template <int MODE>
 __device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3 : 10], int tt, int lane, int w,
-                                                VjpLds& L) {
+                                                VjpLds<MODE>& L) {
 #pragma unroll
   for (int ch = 0; ch < (MODE == 0 ? 3 : 10); ++ch) {
     const float v = wave_sum(acc[ch]);
@@ -1158,45 +1239,57 @@ __device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3
   }
 }
 
+// Passes over ring KIND: full ones while 64 pairs are queued, then a partial
+// one only if pairs of the previous triangle are still queued.
+template <int MODE, int KIND>
+__device__ __forceinline__ void vjp_lanes_drain(VjpRing& q, const uint16_t* ring, bool prev_open, const float* r,
+                                                const float* r_prev, int tag, const float4* __restrict__ erec,
+                                                int64_t ew, int lane, float (&acc)[MODE == 0 ? 3 : 10],
+                                                float (&acc_prev)[MODE == 0 ? 3 : 10]) {
+  while (q.tail - q.head >= 64) {
+    vjp_lanes_pass<MODE, KIND>(ring, q.head, 64, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+    q.head += 64;
+  }
+  if (prev_open && q.head < q.prev_end) {
+    vjp_lanes_pass<MODE, KIND>(ring, q.head, q.tail - q.head, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+    q.head = q.tail;
+  }
+}
+
 // One triangle with the queue bookkeeping: full passes whenever 64 pairs are
-// queued; the previous triangle (at most one other is open) is finished by a
-// partial pass only if some of its pairs are still queued, so most passes are
-// full.  A triangle is closed (reduced into L.tot) once none of its pairs is
-// queued.
+// queued in a ring; the previous triangle (at most one other is open) is
+// finished by partial passes only where some of its pairs are still queued, so
+// most passes are full.  A triangle is closed (reduced into L.tot) once none
+// of its pairs is queued in either ring.
 template <int MODE>
 __device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int tt, const float (&kx)[vjp_j(MODE)],
                                                const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
                                                const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
-                                               uint32_t vm, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
+                                               int rem, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
                                                float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)],
                                                const float4* __restrict__ erec, int64_t ew, float tpx, float tpy,
-                                               float tpz, int lane, int w, VjpLds& L, int& head, int& tail,
-                                               bool& prev_open, int& prev_end, const float*& r_prev,
+                                               float tpz, int lane, int w, VjpLds<MODE>& L, VjpRing (&rq)[2],
+                                               bool& prev_open, const float*& r_prev,
                                                float (&acc_prev)[MODE == 0 ? 3 : 10]) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   float acc[NC];
 #pragma unroll
   for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
   const int tag = tt & 1;
-  vjp_lanes_main<MODE>(r, start, tag, kx, ky, kz, amp, phw, vm, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w], tail,
-                       acc);
-  while (tail - head >= 64) {
-    vjp_lanes_pass<MODE>(L.queue[w], head, 64, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
-    head += 64;
-  }
-  if (prev_open && head < prev_end) {
-    vjp_lanes_pass<MODE>(L.queue[w], head, tail - head, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
-    head = tail;
-  }
+  vjp_lanes_main<MODE>(r, start, tag, kx, ky, kz, amp, phw, rem, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w],
+                       rq, acc);
+  vjp_lanes_drain<MODE, 0>(rq[0], L.queue[w][0], prev_open, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+  vjp_lanes_drain<MODE, 1>(rq[1], L.queue[w][1], prev_open, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
   if (prev_open) vjp_lanes_close<MODE>(acc_prev, tt - 1, lane, w, L);
-  if (head == tail) {
+  if (rq[0].head == rq[0].tail && rq[1].head == rq[1].tail) {
     vjp_lanes_close<MODE>(acc, tt, lane, w, L);
     prev_open = false;
   } else {
 #pragma unroll
     for (int ch = 0; ch < NC; ++ch) acc_prev[ch] = acc[ch];
     prev_open = true;
-    prev_end = tail;
+    rq[0].prev_end = rq[0].tail;
+    rq[1].prev_end = rq[1].tail;
     r_prev = r;
   }
 }
@@ -1205,7 +1298,7 @@ template <int MODE>
 __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, int nt, int t0, int t1,
                                                const float4* __restrict__ erec, int64_t nE, int64_t e_begin,
                                                int n_sub, float tpx, float tpy, float tpz,
-                                               float* __restrict__ part_out, VjpLds& L) {
+                                               float* __restrict__ part_out, VjpLds<MODE>& L) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   constexpr int J = vjp_j(MODE);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1213,7 +1306,8 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
     const int64_t ew = e_begin + (int64_t)g * vjp_chunk(MODE) + (int64_t)w * 64 * J;
     float kx[J], ky[J], kz[J], amp[J], phw[J];
     float Xr[J], Xi[J], Yr[J], Yi[J];
-    uint32_t vm = 0;
+    // entries held by this wave: the first rem of its 64 J (wave-uniform)
+    const int rem = __builtin_amdgcn_readfirstlane((int)max<int64_t>(0, min<int64_t>(nE - ew, 64 * J)));
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int64_t e = ew + 64 * j + lane;
@@ -1226,12 +1320,11 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
         kz[j] = A.z;
         amp[j] = C.x;
         phw[j] = C.y;
-        vm |= 1u << j;
       }
     }
     for (int tb = t0; tb < t1; tb += VJP_TB) {
       const int tn = min(VJP_TB, t1 - tb);
-      int head = 0, tail = 0, prev_end = 0;
+      VjpRing rq[2] = {{0, 0, 0}, {0, 0, 0}};
       bool prev_open = false;
       const float* r_prev = rec + (size_t)tb * TRI_REC;
       float acc_prev[NC];
@@ -1239,19 +1332,23 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
       for (int ch = 0; ch < NC; ++ch) acc_prev[ch] = 0.0f;
       for (int tt = 0; tt < tn; tt += 2) {
         const float* r = rec + (size_t)(tb + tt) * TRI_REC;
-        vjp_lanes_step<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, vm, Xr, Xi, Yr, Yi, erec, ew,
-                             tpx, tpy, tpz, lane, w, L, head, tail, prev_open, prev_end, r_prev, acc_prev);
+        vjp_lanes_step<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, rem, Xr, Xi, Yr, Yi,
+                             erec, ew, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
         if (tt + 1 < tn)
-          vjp_lanes_step<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, vm, Yr, Yi, Xr, Xi,
-                               erec, ew, tpx, tpy, tpz, lane, w, L, head, tail, prev_open, prev_end, r_prev,
-                               acc_prev);
+          vjp_lanes_step<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, rem, Yr, Yi, Xr,
+                               Xi, erec, ew, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
       }
       if (prev_open) {
         // only the last triangle (tn - 1) is still open: finish its pairs
         float none[NC];
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) none[ch] = 0.0f;
-        vjp_lanes_pass<MODE>(L.queue[w], head, tail - head, r_prev, r_prev, (tn & 1), erec, ew, lane, none, acc_prev);
+        if (rq[0].tail > rq[0].head)
+          vjp_lanes_pass<MODE, 0>(L.queue[w][0], rq[0].head, rq[0].tail - rq[0].head, r_prev, r_prev, (tn & 1), erec,
+                                  ew, lane, none, acc_prev);
+        if (rq[1].tail > rq[1].head)
+          vjp_lanes_pass<MODE, 1>(L.queue[w][1], rq[1].head, rq[1].tail - rq[1].head, r_prev, r_prev, (tn & 1), erec,
+                                  ew, lane, none, acc_prev);
         vjp_lanes_close<MODE>(acc_prev, tn - 1, lane, w, L);
       }
       __syncthreads();
@@ -1276,7 +1373,7 @@ template <int MODE>
 __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3) k_vjp_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb,
                                                          const float4* __restrict__ erec, int64_t nE, int n_sub,
                                                          float* __restrict__ part) {
-  __shared__ VjpLds L;
+  __shared__ VjpLds<MODE> L;
   constexpr int NC = MODE == 0 ? 3 : 10;
   const int t0 = blockIdx.y * tpb;
   const int64_t e_begin = (int64_t)blockIdx.x * n_sub * vjp_chunk(MODE);
@@ -1300,7 +1397,7 @@ __device__ __forceinline__ int next_item(int* counter, int* slot) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T) k_batch_fwd(const SweepItem* __restrict__ items, int n_items,
+__global__ void __launch_bounds__(SWEEP_T, 7) k_batch_fwd(const SweepItem* __restrict__ items, int n_items,
                                                          const SweepReq* __restrict__ reqs, int* __restrict__ counter) {
   __shared__ int slot;
   __shared__ FwdLds L;
@@ -1322,7 +1419,7 @@ __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3)
                 int* __restrict__ counter) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   __shared__ int slot;
-  __shared__ VjpLds L;
+  __shared__ VjpLds<MODE> L;
   for (;;) {
     const int it = next_item(counter, &slot);
     if (it >= n_items) return;
