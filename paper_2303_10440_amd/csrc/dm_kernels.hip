@@ -61,10 +61,20 @@ __device__ __forceinline__ float pick(bool c, float a, float b) {
   return c ? a : b;
 }
 
+// A polynomial coefficient of the stable schemes, made opaque where it is
+// used.  Those schemes run only in the queue passes; with plain literals the
+// compiler materialises their coefficients in vector registers once, ahead
+// of the sweep loops, and keeps them live through the main loop, where the
+// registers are needed.
+__device__ __forceinline__ float kc(float c) {
+  asm volatile("" : "+s"(c));
+  return c;
+}
+
 // sin(x)/x for x >= 0 given sin(x): polynomial below 0.5, quotient above.
 __device__ __forceinline__ float sinc_from(float x, float sinx, float inv_x) {
   const float x2 = x * x;
-  const float p = fmaf(x2, fmaf(x2, fmaf(x2, -1.9841269841e-4f, 8.3333333333e-3f), -0.16666666667f), 1.0f);
+  const float p = fmaf(x2, fmaf(x2, fmaf(x2, kc(-1.9841269841e-4f), kc(8.3333333333e-3f)), kc(-0.16666666667f)), 1.0f);
   return pick(x < 0.5f, p, sinx * inv_x);
 }
 
@@ -102,9 +112,9 @@ __device__ __forceinline__ float wrap(float r) { return __builtin_amdgcn_fractf(
 // Series coefficients of DD3 about the node mean (centred phases a_p,
 // E2 = sum a_p a_q, E3 = a_0 a_1 a_2):  Phi = pre + i pim.
 __device__ __forceinline__ void series_phi(float E2, float E3, float& pre, float& pim) {
-  pre = fmaf(E2, fmaf(E2, fmaf(E2, 2.4801587302e-5f, 1.3888888889e-3f), 4.1666666667e-2f), 0.5f) -
-        E3 * E3 * 2.4801587302e-5f;
-  pim = E3 * fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
+  const float c6 = kc(2.4801587302e-5f);
+  pre = fmaf(E2, fmaf(E2, fmaf(E2, c6, kc(1.3888888889e-3f)), kc(4.1666666667e-2f)), 0.5f) - E3 * E3 * c6;
+  pim = E3 * fmaf(E2, fmaf(E2, kc(8.2671957672e-6f), kc(3.9682539683e-4f)), kc(8.3333333333e-3f));
 }
 
 // Reciprocals of S = 2 pi s and of the half gaps x1, x2 clamped at 1/2 (the
@@ -188,10 +198,10 @@ __device__ __forceinline__ void vjp_pair_series(float t1, float d2, float d3, fl
     float pre, pim;
     series_phi(E2, E3, pre, pim);
     // d Phi / d e2 and d Phi / d e3 (e2 = -E2, e3 = i E3 of the centred nodes)
-    const float p2r = fmaf(E2, fmaf(E2, -7.4404761905e-5f, -2.7777777778e-3f), -4.1666666667e-2f);
-    const float p2i = -E3 * fmaf(E2, 1.6534391534e-5f, 3.9682539683e-4f);
-    const float p3r = fmaf(E2, fmaf(E2, 8.2671957672e-6f, 3.9682539683e-4f), 8.3333333333e-3f);
-    const float p3i = E3 * fmaf(E2, 1.6534391534e-6f, 4.9603174603e-5f);
+    const float p2r = fmaf(E2, fmaf(E2, kc(-7.4404761905e-5f), kc(-2.7777777778e-3f)), kc(-4.1666666667e-2f));
+    const float p2i = -E3 * fmaf(E2, kc(1.6534391534e-5f), kc(3.9682539683e-4f));
+    const float p3r = fmaf(E2, fmaf(E2, kc(8.2671957672e-6f), kc(3.9682539683e-4f)), kc(8.3333333333e-3f));
+    const float p3i = E3 * fmaf(E2, kc(1.6534391534e-6f), kc(4.9603174603e-5f));
     const float r = wrap(t1 + m);
     const float c = __builtin_amdgcn_cosf(r), sn = -__builtin_amdgcn_sinf(r);
     // WG = W e^{-2 pi i (t1 + m)}
@@ -228,15 +238,17 @@ __device__ __forceinline__ void vjp_pair_sorted(float t1, float d2, float d3, fl
   float psi1, psi2;
   {
     const float G = 2.0f * x1, G2 = G * G;
-    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, -2.7557319224e-6f, 1.9841269841e-4f), -8.3333333333e-3f),
-                               0.16666666667f);
+    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, kc(-2.7557319224e-6f), kc(1.9841269841e-4f)),
+                                         kc(-8.3333333333e-3f)),
+                               kc(0.16666666667f));
     const float ig = 0.5f * q.invX1;
     psi1 = pick(x1 < 0.5f, ser, fmaf(-2.0f * s1, c1, G) * ig * ig);
   }
   {
     const float G = 2.0f * x2, G2 = G * G;
-    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, -2.7557319224e-6f, 1.9841269841e-4f), -8.3333333333e-3f),
-                               0.16666666667f);
+    const float ser = G * fmaf(G2, fmaf(G2, fmaf(G2, kc(-2.7557319224e-6f), kc(1.9841269841e-4f)),
+                                         kc(-8.3333333333e-3f)),
+                               kc(0.16666666667f));
     const float ig = 0.5f * q.invX2;
     psi2 = pick(x2 < 0.5f, ser, fmaf(-2.0f * s2, c2, G) * ig * ig);
   }
@@ -1105,7 +1117,7 @@ template <int MODE>
 __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int tag, const float (&kx)[vjp_j(MODE)],
                                                const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
                                                const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
-                                               int rem, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
+                                               float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
                                                float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)], float tpx,
                                                float tpy, float tpz, int lane, uint16_t (*ring)[vjp_ring<MODE>()],
                                                VjpRing (&rq)[2], float (&acc)[MODE == 0 ? 3 : 10]) {
@@ -1156,16 +1168,14 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
         acc[3 + 3 * p] = fmaf(zp, x2, acc[3 + 3 * p]);
       }
     }
-    // Ballots of plain compares are the compares' own lane masks; the lanes
-    // holding entries are the first cnt of the wave (cnt wave-uniform).
-    const int cnt = rem - 64 * j;
-    const bool valid = lane < cnt;
-    const uint64_t vmask = cnt >= 64 ? ~0ull : (cnt <= 0 ? 0ull : (1ull << cnt) - 1ull);
-    const uint64_t bs = __builtin_amdgcn_ballot_w64(small) & vmask;
-    const uint64_t bc = __builtin_amdgcn_ballot_w64(close) & vmask & ~bs;
+    // Ballots of plain compares are the compares' own lane masks.  Lanes past
+    // the end of the band (all phases 0) are queued too and skipped by the
+    // passes.
+    const uint64_t bs = __builtin_amdgcn_ballot_w64(small);
+    const uint64_t bc = __builtin_amdgcn_ballot_w64(close) & ~bs;
     const uint16_t item = (uint16_t)((tag << 9) | (j << 6) | lane);
     if (bs) {
-      if (small && valid) {
+      if (small) {
         const int pos = rq[0].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bs >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bs, 0u));
         ring[0][pos & (vjp_ring<MODE>() - 1)] = item;
@@ -1173,7 +1183,7 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
       rq[0].tail += __popcll(bs);
     }
     if (bc) {
-      if (close && !small && valid) {
+      if (close && !small) {
         const int pos = rq[1].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bc >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bc, 0u));
         ring[1][pos & (vjp_ring<MODE>() - 1)] = item;
@@ -1188,19 +1198,21 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
 // Stable scheme (KIND 0 series, 1 sorted) for n queued pairs from ring
 // position head, on full waves: pairs tagged cur_tag belong to triangle r_cur
 // (sums into acc_cur), the others to the previous triangle r_prev (acc_prev).
+// erec_w points at the wave's first entry; n_w of its entries lie in the band
+// (queued entries past them are skipped).
 template <int MODE, int KIND>
 __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, int n, const float* r_cur,
-                                               const float* r_prev, int cur_tag, const float4* __restrict__ erec,
-                                               int64_t ew, int lane, float (&acc_cur)[MODE == 0 ? 3 : 10],
+                                               const float* r_prev, int cur_tag, const float4* __restrict__ erec_w,
+                                               int n_w, int lane, float (&acc_cur)[MODE == 0 ? 3 : 10],
                                                float (&acc_prev)[MODE == 0 ? 3 : 10]) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   wave_lds_sync();
-  if (lane < n) {
-    const int it = ring[(head + lane) & (vjp_ring<MODE>() - 1)];
+  const int it = lane < n ? ring[(head + lane) & (vjp_ring<MODE>() - 1)] : 0;
+  const int eo = 64 * ((it >> 6) & 7) + (it & 63);   // entry offset within the wave's 64 J
+  if (lane < n && eo < n_w) {
     const bool cur = (it >> 9) == cur_tag;
     const float* r = cur ? r_cur : r_prev;
-    const int64_t e = ew + 64 * ((it >> 6) & 7) + (it & 63);
-    const float4 A = erec[ERC * e], B = erec[ERC * e + 1];
+    const float4 A = erec_w[ERC * eo], B = erec_w[ERC * eo + 1];
     float tv, a, b, wf = 0.0f, z[3];
     tri_phases(A.x, A.y, A.z, r, tv, a, b);
     if (KIND == 0)
@@ -1243,15 +1255,15 @@ __device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3
 // one only if pairs of the previous triangle are still queued.
 template <int MODE, int KIND>
 __device__ __forceinline__ void vjp_lanes_drain(VjpRing& q, const uint16_t* ring, bool prev_open, const float* r,
-                                                const float* r_prev, int tag, const float4* __restrict__ erec,
-                                                int64_t ew, int lane, float (&acc)[MODE == 0 ? 3 : 10],
+                                                const float* r_prev, int tag, const float4* __restrict__ erec_w,
+                                                int n_w, int lane, float (&acc)[MODE == 0 ? 3 : 10],
                                                 float (&acc_prev)[MODE == 0 ? 3 : 10]) {
   while (q.tail - q.head >= 64) {
-    vjp_lanes_pass<MODE, KIND>(ring, q.head, 64, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+    vjp_lanes_pass<MODE, KIND>(ring, q.head, 64, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
     q.head += 64;
   }
   if (prev_open && q.head < q.prev_end) {
-    vjp_lanes_pass<MODE, KIND>(ring, q.head, q.tail - q.head, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+    vjp_lanes_pass<MODE, KIND>(ring, q.head, q.tail - q.head, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
     q.head = q.tail;
   }
 }
@@ -1265,9 +1277,9 @@ template <int MODE>
 __device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int tt, const float (&kx)[vjp_j(MODE)],
                                                const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
                                                const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
-                                               int rem, float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
+                                               float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
                                                float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)],
-                                               const float4* __restrict__ erec, int64_t ew, float tpx, float tpy,
+                                               const float4* __restrict__ erec_w, int n_w, float tpx, float tpy,
                                                float tpz, int lane, int w, VjpLds<MODE>& L, VjpRing (&rq)[2],
                                                bool& prev_open, const float*& r_prev,
                                                float (&acc_prev)[MODE == 0 ? 3 : 10]) {
@@ -1276,10 +1288,10 @@ __device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int t
 #pragma unroll
   for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
   const int tag = tt & 1;
-  vjp_lanes_main<MODE>(r, start, tag, kx, ky, kz, amp, phw, rem, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w],
+  vjp_lanes_main<MODE>(r, start, tag, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w],
                        rq, acc);
-  vjp_lanes_drain<MODE, 0>(rq[0], L.queue[w][0], prev_open, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
-  vjp_lanes_drain<MODE, 1>(rq[1], L.queue[w][1], prev_open, r, r_prev, tag, erec, ew, lane, acc, acc_prev);
+  vjp_lanes_drain<MODE, 0>(rq[0], L.queue[w][0], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
+  vjp_lanes_drain<MODE, 1>(rq[1], L.queue[w][1], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
   if (prev_open) vjp_lanes_close<MODE>(acc_prev, tt - 1, lane, w, L);
   if (rq[0].head == rq[0].tail && rq[1].head == rq[1].tail) {
     vjp_lanes_close<MODE>(acc, tt, lane, w, L);
@@ -1301,13 +1313,14 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
                                                float* __restrict__ part_out, VjpLds<MODE>& L) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   constexpr int J = vjp_j(MODE);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index is wave-uniform: entry addresses get a scalar base
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int g = 0; g < n_sub; ++g) {
     const int64_t ew = e_begin + (int64_t)g * vjp_chunk(MODE) + (int64_t)w * 64 * J;
+    const float4* erec_w = erec + ERC * ew;
+    const int n_w = (int)max<int64_t>(0, min<int64_t>(nE - ew, 64 * J));   // entries of this wave in the band
     float kx[J], ky[J], kz[J], amp[J], phw[J];
     float Xr[J], Xi[J], Yr[J], Yi[J];
-    // entries held by this wave: the first rem of its 64 J (wave-uniform)
-    const int rem = __builtin_amdgcn_readfirstlane((int)max<int64_t>(0, min<int64_t>(nE - ew, 64 * J)));
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int64_t e = ew + 64 * j + lane;
@@ -1332,11 +1345,11 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
       for (int ch = 0; ch < NC; ++ch) acc_prev[ch] = 0.0f;
       for (int tt = 0; tt < tn; tt += 2) {
         const float* r = rec + (size_t)(tb + tt) * TRI_REC;
-        vjp_lanes_step<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, rem, Xr, Xi, Yr, Yi,
-                             erec, ew, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
+        vjp_lanes_step<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi,
+                             erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
         if (tt + 1 < tn)
-          vjp_lanes_step<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, rem, Yr, Yi, Xr,
-                               Xi, erec, ew, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
+          vjp_lanes_step<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, Yr, Yi, Xr,
+                               Xi, erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
       }
       if (prev_open) {
         // only the last triangle (tn - 1) is still open: finish its pairs
@@ -1344,11 +1357,11 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) none[ch] = 0.0f;
         if (rq[0].tail > rq[0].head)
-          vjp_lanes_pass<MODE, 0>(L.queue[w][0], rq[0].head, rq[0].tail - rq[0].head, r_prev, r_prev, (tn & 1), erec,
-                                  ew, lane, none, acc_prev);
+          vjp_lanes_pass<MODE, 0>(L.queue[w][0], rq[0].head, rq[0].tail - rq[0].head, r_prev, r_prev, (tn & 1), erec_w,
+                                  n_w, lane, none, acc_prev);
         if (rq[1].tail > rq[1].head)
-          vjp_lanes_pass<MODE, 1>(L.queue[w][1], rq[1].head, rq[1].tail - rq[1].head, r_prev, r_prev, (tn & 1), erec,
-                                  ew, lane, none, acc_prev);
+          vjp_lanes_pass<MODE, 1>(L.queue[w][1], rq[1].head, rq[1].tail - rq[1].head, r_prev, r_prev, (tn & 1), erec_w,
+                                  n_w, lane, none, acc_prev);
         vjp_lanes_close<MODE>(acc_prev, tn - 1, lane, w, L);
       }
       __syncthreads();
@@ -1388,6 +1401,40 @@ __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3) k_vjp_lanes(GridC 
 // workgroup takes the next item from a global counter; every item writes its
 // own partial slot, so the results do not depend on which workgroup ran which
 // item.
+// Work items and requests are read after the sweeps' stores, so the compiler
+// cannot keep them in scalar registers by itself; they are wave-uniform, and
+// these copies say so (otherwise they occupy vector registers in the sweeps).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ SweepItem uni(const SweepItem& w) { return {uni(w.kind), uni(w.req), uni(w.x0), uni(w.c)}; }
+__device__ __forceinline__ SweepReq uni(const SweepReq& q) {
+  SweepReq u;
+  u.mode = uni(q.mode);
+  u.nE = uni(q.nE);
+  u.nt = uni(q.nt);
+  u.tpc = uni(q.tpc);
+  u.epc = uni(q.epc);
+  u.vsub = uni(q.vsub);
+  u.vtpb = uni(q.vtpb);
+  u.pad = 0;
+  u.tpx = uni(q.tpx);
+  u.tpy = uni(q.tpy);
+  u.tpz = uni(q.tpz);
+  u.pad2 = 0.0f;
+  u.kf = uni(q.kf);
+  u.rec = uni(q.rec);
+  u.fpart = uni(q.fpart);
+  u.erec = uni(q.erec);
+  u.vpart = uni(q.vpart);
+  return u;
+}
+
 __device__ __forceinline__ int next_item(int* counter, int* slot) {
   if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
   __syncthreads();
@@ -1404,8 +1451,8 @@ __global__ void __launch_bounds__(SWEEP_T, 7) k_batch_fwd(const SweepItem* __res
   for (;;) {
     const int it = next_item(counter, &slot);
     if (it >= n_items) return;
-    const SweepItem w = items[it];
-    const SweepReq q = reqs[w.req];
+    const SweepItem w = uni(items[it]);
+    const SweepReq q = uni(reqs[w.req]);
     const int t0 = w.c * q.tpc, t1 = min(q.nt, t0 + q.tpc);
     fwd_lanes_tile<MODE>(q.kf, q.nE, q.rec, t0, t1, w.x0, q.fpart + (size_t)w.c * q.nE, L);
   }
@@ -1423,8 +1470,8 @@ __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3)
   for (;;) {
     const int it = next_item(counter, &slot);
     if (it >= n_items) return;
-    const SweepItem w = items[it];
-    const SweepReq q = reqs[w.req];
+    const SweepItem w = uni(items[it]);
+    const SweepReq q = uni(reqs[w.req]);
     const int64_t e_begin = (int64_t)w.c * q.epc;
     const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + vjp_chunk(MODE) - 1) / vjp_chunk(MODE));
     const int t1 = min(q.nt, w.x0 + q.vtpb);
