@@ -120,6 +120,10 @@ struct dm_handle {
   rocfft_execution_info exec_info = nullptr;
   hipEvent_t last_ev = nullptr;
   bool have_last = false;
+  // Second stream of batched calls (created on first use, default priority)
+  // and the events that fork work onto it and join it back.
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int topo_count = 0;
   size_t topo_bytes = 0;
   bool timing = false;
@@ -600,6 +604,13 @@ dm_status begin_call(dm_handle* h, hipStream_t s) {
   return DM_OK;
 }
 
+dm_status ensure_aux(dm_handle* h) {
+  if (!h->aux) HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+  if (!h->fork_ev) HIP_TRY(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+  if (!h->join_ev) HIP_TRY(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
+  return DM_OK;
+}
+
 dm_status end_call(dm_handle* h, hipStream_t s) {
   HIP_TRY(hipEventRecord(h->last_ev, s));
   h->have_last = true;
@@ -929,24 +940,13 @@ void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
   L.total += 256;
 }
 
-// Enqueues a planned batch on s: every request's pre-steps, the shared
-// persistent launch and the post-steps of the requests in it, then each large
-// request's own sweeps and post-steps.  With req_done, an event is recorded
-// after each request's last step (req_done[i] for request i), so that a
-// caller can hand out results as they complete.
-dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s,
-                        const std::vector<hipEvent_t>* req_done = nullptr) {
+// The part of a batch after the pre-steps: the shared persistent launch and
+// its requests' post-steps on s, then the large requests, alternating between
+// s and s2 (the same stream when there is no second one).
+template <typename Done>
+dm_status enqueue_batch_rest(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s,
+                             hipStream_t s2, Done& done) {
   const size_t n = P.size();
-  L.reqs.resize(n);
-  for (size_t i = 0; i < n; ++i) {
-    P[i].base = base + L.off[i];
-    L.reqs[i] = sweep_req(P[i]);
-  }
-  auto done = [&](size_t i) -> dm_status {
-    if (req_done && (*req_done)[i]) HIP_TRY(hipEventRecord((*req_done)[i], s));
-    return DM_OK;
-  };
-  for (size_t i = 0; i < n; ++i) DM_TRY(stage_pre(h, P[i], s));
   if (!L.items.empty()) {
     HIP_TRY(hipMemcpyAsync(base + L.o_items, L.items.data(), L.items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
                            s));
@@ -960,15 +960,58 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
   for (size_t i = 0; i < n; ++i)
     if (!P[i].direct) {
       DM_TRY(stage_post(h, P[i], s));
-      DM_TRY(done(i));
+      DM_TRY(done(i, s));
     }
+  int k = 0;
   for (size_t i = 0; i < n; ++i)
     if (P[i].direct) {
-      DM_TRY(stage_sweeps(h, P[i], s));
-      DM_TRY(stage_post(h, P[i], s));
-      DM_TRY(done(i));
+      const hipStream_t st = (k++ & 1) ? s : s2;
+      DM_TRY(stage_sweeps(h, P[i], st));
+      DM_TRY(stage_post(h, P[i], st));
+      DM_TRY(done(i, st));
     }
   return DM_OK;
+}
+
+// Enqueues a planned batch on s: every request's pre-steps, the shared
+// persistent launch and the post-steps of the requests in it, then each large
+// request's own sweeps and post-steps.  Large requests alternate between s
+// and the handle's second stream (forked after the pre-steps, joined back
+// into s at the end), so one request's post-steps and the tail of its sweeps
+// overlap the next one's sweeps; each request works in its own region of the
+// batch memory, and its FFTs get its own work buffer.  With req_done, an
+// event is recorded after each request's last step (req_done[i] for request
+// i, on the stream that ran it), so that a caller can hand out results as
+// they complete.
+dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s,
+                        const std::vector<hipEvent_t>* req_done = nullptr) {
+  const size_t n = P.size();
+  L.reqs.resize(n);
+  int n_direct = 0;
+  for (size_t i = 0; i < n; ++i) {
+    P[i].base = base + L.off[i];
+    L.reqs[i] = sweep_req(P[i]);
+    if (P[i].direct && !P[i].empty) ++n_direct;
+  }
+  auto done = [&](size_t i, hipStream_t st) -> dm_status {
+    if (req_done && (*req_done)[i]) HIP_TRY(hipEventRecord((*req_done)[i], st));
+    return DM_OK;
+  };
+  for (size_t i = 0; i < n; ++i) DM_TRY(stage_pre(h, P[i], s));
+  hipStream_t s2 = s;
+  if (n_direct >= 2) {
+    DM_TRY(ensure_aux(h));
+    HIP_TRY(hipEventRecord(h->fork_ev, s));
+    HIP_TRY(hipStreamWaitEvent(h->aux, h->fork_ev, 0));
+    s2 = h->aux;
+  }
+  const dm_status st = enqueue_batch_rest(h, P, L, base, s, s2, done);
+  if (s2 != s) {
+    // join even after a failed enqueue, so that s never runs ahead of s2
+    HIP_TRY(hipEventRecord(h->join_ev, s2));
+    HIP_TRY(hipStreamWaitEvent(s, h->join_ev, 0));
+  }
+  return st;
 }
 
 }  // namespace
@@ -1019,6 +1062,9 @@ dm_status dm_destroy(dm_handle* h) {
   for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
   if (h->last_ev) (void)hipEventDestroy(h->last_ev);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   delete h;
   return DM_OK;
 }

@@ -153,3 +153,46 @@ def test_large_request_in_a_batch_runs_its_own_sweeps(dm, handle):
     assert torch.equal(img, single[2]) and torch.equal(dv, single[0]) and torch.equal(ds, single[1])
     for a, b in zip(out[0], alone[0]):
         assert torch.equal(a, b)
+
+
+def test_several_large_requests_alternate_streams(dm, handle):
+    """Three large requests (the single cell in both density modes, and the
+    volume cell with another PSF) and two small ones in one batch: the large
+    ones run their own sweeps, alternating between the caller's stream and
+    the handle's second stream, and their outputs are bitwise the single
+    call's; the small ones share the persistent launch and match a batch of
+    themselves alone bitwise.  The batch is complete when the caller's stream
+    is (read right after it, with no device-wide synchronisation)."""
+    import torch
+    big = configs.cfg3(VOLUME)
+    bigs = configs.cfg3(SURFACE)
+    small = configs.cfg1()
+    tb = handle.topology(big.F, n_verts=len(big.V))
+    tbs = handle.topology(bigs.F, n_verts=len(bigs.V))
+    ts = handle.topology(small.F, n_verts=len(small.V))
+    rng = np.random.default_rng(31)
+    Gb = dev(rng.standard_normal(big.grid.n).astype(np.float32))
+    Gbs = dev(rng.standard_normal(bigs.grid.n).astype(np.float32))
+    Gs = dev(rng.standard_normal(small.grid.n).astype(np.float32))
+    sig2 = configs.psf_diag(0.17, 0.5)
+    reqs = [(dev(big.V), tb, big.sigma, big.grid, Gb),
+            (dev(small.V), ts, small.sigma, small.grid, Gs),
+            (dev(bigs.V), tbs, bigs.sigma, bigs.grid, Gbs),
+            (dev(small.V) * 1.01, ts, small.sigma, small.grid, Gs),
+            (dev(big.V), tb, sig2, big.grid, Gb)]
+    large = {0, 2, 4}
+    refs = []
+    for i, r in enumerate(reqs):
+        if i in large:
+            dv, ds, img = dm.render_vjp(handle, *r, want_image=True)
+            refs.append((img, dv, ds))
+        else:
+            refs.append(dm.batch_run(handle, [r])[0])
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    out = dm.batch_run(handle, reqs)
+    s.synchronize()
+    for i, (o, ref) in enumerate(zip(out, refs)):
+        eq = all(torch.equal(a, b) for a, b in zip(o, ref))
+        say(f"request {i} ({'own sweeps' if i in large else 'shared launch'}): outputs equal: {eq}")
+        assert eq
