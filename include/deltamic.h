@@ -274,10 +274,17 @@ dm_status dm_render_otf_vjp(dm_handle* h, const dm_mesh* mesh, const void* otf, 
  * Eq. 6/9-10) execute in one persistent launch whose workgroups draw work
  * tiles from a shared queue, longest first; the small per-request steps
  * (band, mesh prep, FFTs, adjoint weights, reductions) run around it on the
- * same stream.  Each request's tiles and summation order depend on that
- * request alone, so its results are bitwise the same whatever else is in the
- * batch (and agree with dm_render_vjp to rounding).  All validation happens
- * before anything is enqueued; on error no output is written. */
+ * same stream.  A request of at least 5e8 (band entry, triangle) pairs fills
+ * the GPU by itself: it runs the sweep launches of dm_render_vjp instead, so
+ * its results are bitwise dm_render_vjp's; when a batch holds two or more of
+ * these, they alternate between `stream` and a second stream owned by the
+ * handle, which starts after the batch's pre-steps on `stream` and which
+ * `stream` waits for before anything enqueued on it after this call (work
+ * on `stream` sees the whole batch done).  Each request's tiles and
+ * summation order depend on that request alone, so its results are bitwise
+ * the same whatever else is in the batch (and agree with dm_render_vjp to
+ * rounding).  All validation happens before anything is enqueued; on error
+ * no output is written. */
 dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* stream);
 
 /* --------------------------------------------------------------- serving */
