@@ -43,7 +43,7 @@ constexpr float SERIES_REV = 0.15915494309189535f;   // 1 / (2 pi)
 constexpr float INV_TWO_PI_F = 0.15915494309189535f;
 // Closed (Lagrange) form of the gradient pair when every node gap is at least
 // LAG_GAP revolutions and the spread at least SERIES_REV; other pairs go to
-// vjp_pair.  Its float32 rounding grows like 1 / (2 pi gap)^2; at this gap the
+// vjp_pair_series / vjp_pair_sorted.  Its float32 rounding grows like 1 / (2 pi gap)^2; at this gap the
 // vertex gradients stay within about 1e-5 relative of the float64 result, an
 // order of magnitude inside the gradient tolerance.
 constexpr float LAG_GAP = 0.01f;
@@ -1051,9 +1051,10 @@ __device__ __forceinline__ float wave_sum(float v) {
 // of vjp_chunk(MODE) band entries (in chunk g: wave w, step j, lane l -> entry
 // 64 (w J + j) + l) and a range of at most VJP_TPB_MAX strip-ordered triangles,
 // which are wave-uniform; the weighted phase factors of the two vertices a
-// triangle shares with the previous one are carried over.  Pairs whose nodes are too close for the closed form are
-// queued in LDS and evaluated by vjp_pair after each triangle, so the stable
-// branch runs on full waves instead of diverging.  Per triangle the lane sums
+// triangle shares with the previous one are carried over.  Pairs whose nodes
+// are too close for the closed form are queued in LDS, one ring per stable
+// scheme, and evaluated 64 at a time (vjp_lanes_pass), so each scheme runs on
+// full waves instead of diverging.  Per triangle the lane sums
 // are reduced over the wave (wave_sum), over the 4 waves and
 // then over the entry chunks, each in a fixed order, into part_out[NC][nt].
 constexpr int VJP_TB = 32;   // triangles between block-level merges
