@@ -154,3 +154,43 @@ def test_mesh_remove_with_pending_request_is_refused(dm):
             srv.submit(mid, f32_sigma(c.sigma), b[0], b[1], b[2], b[3], b[4])
     finally:
         srv.close()
+
+
+def test_served_large_requests_on_two_streams(dm):
+    """Three requests large enough to run their own sweeps (the single cell,
+    both density modes, and the volume cell with a wider PSF) submitted with
+    small ones: in a batch the large ones alternate between the batch's
+    stream and the handle's second stream, each handed out at its own
+    completion.  Every result equals the same request run alone."""
+    import torch
+    say("serve large requests on two streams")
+    big = configs.cfg3(VOLUME)
+    bigs = configs.cfg3(SURFACE)
+    small = _cells(2, seed=5)
+    wide = configs.psf_diag(0.17, 0.5)
+    jobs = [(big, big.sigma), (small[0], small[0].sigma), (bigs, bigs.sigma), (small[1], small[1].sigma),
+            (big, wide)]
+    srv = dm.Server(0, max_batch=8, max_inflight=2)
+    h = dm.Handle(0)
+    try:
+        mids = {}
+        for c, _ in jobs:
+            if id(c) not in mids:
+                mids[id(c)] = srv.mesh_add(c.V, c.F)
+        bufs = [_buffers(c, 40 + i) for i, (c, _) in enumerate(jobs)]
+        tickets = [srv.submit(mids[id(c)], f32_sigma(sig), b[0], b[1], b[2], b[3], b[4])
+                   for (c, sig), b in zip(jobs, bufs)]
+        res = [srv.poll(t) for t in tickets]
+        say("statuses", [r["status"] for r in res])
+        assert all(r["status"] == 0 for r in res)
+        torch.cuda.synchronize()
+        for i, ((c, sig), b) in enumerate(zip(jobs, bufs)):
+            g, G = b[0], b[1]
+            topo = h.topology(c.F, n_verts=len(c.V))
+            V = torch.tensor(c.V, device="cuda:0")
+            img, dv, ds = dm.batch_run(h, [(V, topo, f32_sigma(sig), g, G)])[0]
+            eq = bool((img == b[2]).all()) and bool((dv == b[3]).all()) and bool((ds == b[4]).all())
+            say(f"request {i}: served equals alone: {eq}")
+            assert eq
+    finally:
+        srv.close()
