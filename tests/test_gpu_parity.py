@@ -246,6 +246,44 @@ def test_cfg3_volume_gradient_at_sampled_vertices(dm, handle, ref):
     assert err < GRAD_TOL, err
 
 
+def test_largest_serving_shape_at_sampled_outputs(dm, handle, ref):
+    """The largest request of the serving workload: a deformed geodesic
+    sphere of 40,500 triangles in the 256x256x128 grid (unit voxels,
+    sigma_xy = 1, band about 1.5M entries, |k| up to 128, so vertex phases
+    reach about 40 revolutions), in the launch configuration of a single call.
+    Checked on what the oracle can evaluate at this size: the mesh transform
+    at 300 sampled frequencies (the extreme ones included), the image's
+    integral (the k = 0 term, the enclosed volume) and the gradients of 4
+    sampled vertices (from the triangles around them)."""
+    import torch
+    say("largest serving shape")
+    c = configs.random_cell(np.random.default_rng(11), 40000, 40000, ((256, 256, 128),), "largest", VOLUME)
+    V, F, g, S = prepared(c, VOLUME)
+    say("  triangles", len(F), "band", dm.band_size(handle, g, S))
+    topo = handle.topology(F, n_verts=len(V))
+    K = _k_samples(g, np.random.default_rng(12))
+    got = dm.mesh_transform(handle, dev(V), topo, g, dev(K)).cpu().numpy().astype(np.complex128)
+    want = ref.mesh_transform(V.astype(np.float64), F, ref.xi_of_k(K, g), g, VOLUME)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say("  transform: max err / scale", err, "rel l2", rel_l2(got, want))
+    assert err < 2e-6 and rel_l2(got, want) < IMG_TOL
+    G = np.random.default_rng(13).standard_normal(g.n).astype(np.float32)
+    dv, _, img = dm.render_vjp(handle, dev(V), topo, S, g, dev(G), want_sigma=False, want_image=True)
+    vol = float(np.real(ref.mesh_transform(V.astype(np.float64), F, np.zeros((1, 3)), g, VOLUME)[0]))
+    dvol = float(np.prod(g.spacing))
+    integral = float(img.double().sum()) * dvol
+    say("  image integral", integral, "volume", vol)
+    assert abs(integral - vol) < IMG_TOL * abs(vol)
+    vs = np.random.default_rng(14).choice(len(V), 4, replace=False)
+    tris = np.nonzero(np.isin(F, vs).any(axis=1))[0]
+    dvw, _ = ref.render_vjp(V.astype(np.float64), F[tris], g, S, G.astype(np.float64))
+    gerr = rel_l2(dv.cpu().numpy()[vs], dvw[vs])
+    say("  gradient rel err at sampled vertices", gerr)
+    assert gerr < GRAD_TOL, gerr
+    del img, dv
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("mode", [VOLUME, SURFACE])
 def test_cfg2_mse_gradient_vs_oracle_and_fd(dm, handle, ref, mode):
     """cfg2: jittered sphere, MSE against a noisy render of the unjittered
