@@ -207,6 +207,36 @@ def test_render_empty_band_gives_zero_image(dm, handle, ref):
     assert float(img.abs().max()) == 0.0
 
 
+def test_mesh_without_triangles(dm, handle, ref):
+    """A mesh with vertices but no triangles: the surface density renders a
+    zero image and zero gradients (vertex and PSF), alone and inside a batch
+    next to a non-empty request, and the mesh transform is zero; the
+    indicator density refuses it (no enclosed region: not a closed
+    surface)."""
+    import torch
+    say("mesh without triangles")
+    c = configs.cfg1(SURFACE)
+    V, F, g, S = prepared(c, SURFACE)
+    V0 = V[:5].copy()
+    F0 = np.zeros((0, 3), np.int32)
+    topo0 = handle.topology(F0, n_verts=len(V0))
+    G = np.random.default_rng(3).standard_normal(g.n).astype(np.float32)
+    dv, ds, img = dm.render_vjp(handle, dev(V0), topo0, S, g, dev(G), want_image=True)
+    assert tuple(dv.shape) == (5, 3)
+    assert float(img.abs().max()) == 0.0 and float(dv.abs().max()) == 0.0 and float(ds.abs().max()) == 0.0
+    K = _k_samples(g, np.random.default_rng(4), n=20)
+    u = dm.mesh_transform(handle, dev(V0), topo0, g, dev(K))
+    assert float(u.abs().max()) == 0.0
+    topo = handle.topology(F, n_verts=len(V))
+    out = dm.batch_run(handle, [(dev(V0), topo0, S, g, dev(G)), (dev(V), topo, S, g, dev(G))])
+    alone = dm.batch_run(handle, [(dev(V), topo, S, g, dev(G))])
+    torch.cuda.synchronize()
+    assert all(float(x.abs().max()) == 0.0 for x in out[0])
+    assert all(torch.equal(a, b) for a, b in zip(out[1], alone[0]))
+    with pytest.raises(dm.DeltamicError):
+        dm.render(handle, dev(V0), topo0, S, g.with_mode(VOLUME))
+
+
 # ------------------------------------------------------------- gradients
 @pytest.mark.parametrize("mode", [VOLUME, SURFACE])
 @pytest.mark.parametrize("name", ["cfg1", "box", "odd_general", "tau0"])
