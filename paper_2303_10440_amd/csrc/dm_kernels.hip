@@ -680,6 +680,22 @@ struct FwdLds {
   float2 fb[4][FWD_J][64];
 };
 
+// Queue item: triangle tag, entry step j and lane.  The lane is made opaque
+// so that the item is built where it is stored, in the rarely taken append
+// branches; otherwise the compiler keeps one precomputed item per step in a
+// vector register through the whole main loop.
+__device__ __forceinline__ uint16_t queue_item(int tag, int j, int lane) {
+  asm volatile("" : "+v"(lane));
+  return (uint16_t)((tag << 9) | (j << 6) | lane);
+}
+// The same item with the lane left visible to the compiler: the batched
+// surface-density gradient sweep spills inside its triangle loop with the
+// opaque form and not with this one (measured on the compiler's resource
+// report), so that kernel alone uses it.
+__device__ __forceinline__ uint16_t plain_item(int tag, int j, int lane) {
+  return (uint16_t)((tag << 9) | (j << 6) | lane);
+}
+
 // One triangle: X holds the phase factors of vertex 1, Y of vertex 2 (both
 // computed here at a strip start); on return X holds those of vertex 3, so
 // the next triangle of the strip is processed with the roles of X and Y
@@ -729,12 +745,11 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
     const uint64_t vmask = cnt >= 64 ? ~0ull : (cnt <= 0 ? 0ull : (1ull << cnt) - 1ull);
     const uint64_t bs = __builtin_amdgcn_ballot_w64(MODE == 0 ? small : !fast) & vmask;
     const uint64_t bc = MODE == 0 ? __builtin_amdgcn_ballot_w64(close) & vmask & ~bs : 0ull;
-    const uint16_t item = (uint16_t)((tag << 9) | (j << 6) | lane);
     if (bs) {
       if ((MODE == 0 ? small : !fast) && valid) {
         const int pos = nq[0] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bs >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bs, 0u));
-        queue[0][pos] = item;
+        queue[0][pos] = queue_item(tag, j, lane);
       }
       nq[0] += __popcll(bs);
     }
@@ -742,7 +757,7 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
       if (close && !small && valid) {
         const int pos = nq[1] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bc >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bc, 0u));
-        queue[1][pos] = item;
+        queue[1][pos] = queue_item(tag, j, lane);
       }
       nq[1] += __popcll(bc);
     }
@@ -1037,14 +1052,13 @@ template <int CTRL, int ROWMASK>
 __device__ __forceinline__ float dpp_src(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
 }
-__device__ __forceinline__ float wave_sum(float v) {
+// Sum over each row of 16 lanes, left in every lane of the row.
+__device__ __forceinline__ float row_sum(float v) {
   v += dpp_src<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
   v += dpp_src<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
   v += dpp_src<0x141, 0xF>(v);   // row_half_mirror
   v += dpp_src<0x140, 0xF>(v);   // row_mirror
-  v += dpp_src<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-  v += dpp_src<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  return v;
 }
 
 // Lane-per-entry gradient sweep.  A block owns n_sub consecutive entry chunks
@@ -1055,7 +1069,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 // are too close for the closed form are queued in LDS, one ring per stable
 // scheme, and evaluated 64 at a time (vjp_lanes_pass), so each scheme runs on
 // full waves instead of diverging.  Per triangle the lane sums
-// are reduced over the wave (wave_sum), over the 4 waves and
+// are reduced over each row of 16 lanes (row_sum), over the rows and waves and
 // then over the entry chunks, each in a fixed order, into part_out[NC][nt].
 constexpr int VJP_TB = 32;   // triangles between block-level merges
 
@@ -1072,7 +1086,7 @@ static_assert(64 + 64 * VJP_J_MAX <= 1024, "ring too small");
 template <int MODE>
 struct VjpLds {
   uint16_t queue[4][2][vjp_ring<MODE>()];
-  float tot[4][VJP_TB][10];
+  float tot[4][4][VJP_TB][MODE == 0 ? 3 : 10];   // [wave][row of 16 lanes][triangle][channel]
   float sum[VJP_TPB_MAX][10];
 };
 
@@ -1114,7 +1128,7 @@ __device__ __forceinline__ void lag_pair_g(float a, float b, bool use, float amp
 // those of vertex 3, so the next triangle of the strip swaps X and Y.  Pairs
 // that need the stable scheme are appended to the wave's ring of queued pairs
 // (ring positions tail.., tagged with the triangle's parity).
-template <int MODE>
+template <int MODE, bool OPQ>
 __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int tag, const float (&kx)[vjp_j(MODE)],
                                                const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
                                                const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
@@ -1174,12 +1188,11 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
     // passes.
     const uint64_t bs = __builtin_amdgcn_ballot_w64(small);
     const uint64_t bc = __builtin_amdgcn_ballot_w64(close) & ~bs;
-    const uint16_t item = (uint16_t)((tag << 9) | (j << 6) | lane);
     if (bs) {
       if (small) {
         const int pos = rq[0].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bs >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bs, 0u));
-        ring[0][pos & (vjp_ring<MODE>() - 1)] = item;
+        ring[0][pos & (vjp_ring<MODE>() - 1)] = OPQ ? queue_item(tag, j, lane) : plain_item(tag, j, lane);
       }
       rq[0].tail += __popcll(bs);
     }
@@ -1187,7 +1200,7 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
       if (close && !small) {
         const int pos = rq[1].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bc >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bc, 0u));
-        ring[1][pos & (vjp_ring<MODE>() - 1)] = item;
+        ring[1][pos & (vjp_ring<MODE>() - 1)] = OPQ ? queue_item(tag, j, lane) : plain_item(tag, j, lane);
       }
       rq[1].tail += __popcll(bc);
     }
@@ -1241,14 +1254,15 @@ __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, i
   }
 }
 
-// Wave sums of one triangle into L.tot[w][tt].
+// Row sums (16 lanes each) of one triangle into L.tot[w][row][tt]; the block
+// merge adds the 4 rows of the 4 waves.
 template <int MODE>
 __device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3 : 10], int tt, int lane, int w,
                                                 VjpLds<MODE>& L) {
 #pragma unroll
   for (int ch = 0; ch < (MODE == 0 ? 3 : 10); ++ch) {
-    const float v = wave_sum(acc[ch]);
-    if (lane == 0) L.tot[w][tt][ch] = v;
+    const float v = row_sum(acc[ch]);
+    if ((lane & 15) == 0) L.tot[w][lane >> 4][tt][ch] = v;
   }
 }
 
@@ -1274,7 +1288,7 @@ __device__ __forceinline__ void vjp_lanes_drain(VjpRing& q, const uint16_t* ring
 // finished by partial passes only where some of its pairs are still queued, so
 // most passes are full.  A triangle is closed (reduced into L.tot) once none
 // of its pairs is queued in either ring.
-template <int MODE>
+template <int MODE, bool OPQ>
 __device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int tt, const float (&kx)[vjp_j(MODE)],
                                                const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
                                                const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
@@ -1289,7 +1303,7 @@ __device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int t
 #pragma unroll
   for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
   const int tag = tt & 1;
-  vjp_lanes_main<MODE>(r, start, tag, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w],
+  vjp_lanes_main<MODE, OPQ>(r, start, tag, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w],
                        rq, acc);
   vjp_lanes_drain<MODE, 0>(rq[0], L.queue[w][0], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
   vjp_lanes_drain<MODE, 1>(rq[1], L.queue[w][1], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
@@ -1307,7 +1321,7 @@ __device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int t
   }
 }
 
-template <int MODE>
+template <int MODE, bool OPQ = true>
 __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, int nt, int t0, int t1,
                                                const float4* __restrict__ erec, int64_t nE, int64_t e_begin,
                                                int n_sub, float tpx, float tpy, float tpz,
@@ -1346,10 +1360,10 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
       for (int ch = 0; ch < NC; ++ch) acc_prev[ch] = 0.0f;
       for (int tt = 0; tt < tn; tt += 2) {
         const float* r = rec + (size_t)(tb + tt) * TRI_REC;
-        vjp_lanes_step<MODE>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi,
+        vjp_lanes_step<MODE, OPQ>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi,
                              erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
         if (tt + 1 < tn)
-          vjp_lanes_step<MODE>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, Yr, Yi, Xr,
+          vjp_lanes_step<MODE, OPQ>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, Yr, Yi, Xr,
                                Xi, erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
       }
       if (prev_open) {
@@ -1368,7 +1382,10 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
       __syncthreads();
       for (int i = threadIdx.x; i < tn * NC; i += SWEEP_T) {
         const int tt = i / NC, ch = i - tt * NC;
-        const float v = (L.tot[0][tt][ch] + L.tot[1][tt][ch]) + (L.tot[2][tt][ch] + L.tot[3][tt][ch]);
+        float v = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww)
+          v += (L.tot[ww][0][tt][ch] + L.tot[ww][1][tt][ch]) + (L.tot[ww][2][tt][ch] + L.tot[ww][3][tt][ch]);
         float& acc_t = L.sum[tb - t0 + tt][ch];
         acc_t = g == 0 ? v : acc_t + v;
       }
@@ -1476,7 +1493,7 @@ __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3)
     const int64_t e_begin = (int64_t)w.c * q.epc;
     const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + vjp_chunk(MODE) - 1) / vjp_chunk(MODE));
     const int t1 = min(q.nt, w.x0 + q.vtpb);
-    vjp_lanes_tile<MODE>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
+    vjp_lanes_tile<MODE, MODE == 0>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
                          q.vpart + (size_t)w.c * NC * q.nt, L);
   }
 }
