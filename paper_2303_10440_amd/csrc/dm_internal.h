@@ -56,10 +56,11 @@ constexpr float PHASE_GRID = 4096.0f;   // 2^12
 constexpr int ERC = 3;
 
 // Lane-per-entry gradient sweep: vjp_j(mode) band entries per lane (entry
-// chunks of 4 waves x 64 lanes x vjp_j(mode) entries); the surface mode's ten
-// accumulators leave room for fewer entries per lane at the same occupancy.
+// chunks of 4 waves x 64 lanes x vjp_j(mode) entries), chosen with the
+// occupancy: 5 per lane at 5 waves per SIMD (volume), 6 at 4 waves (surface,
+// whose ten accumulators per triangle need the larger register budget).
 constexpr int VJP_J_MAX = 8;
-constexpr int vjp_j(int mode) { return mode == 0 ? 5 : 8; }
+constexpr int vjp_j(int mode) { return mode == 0 ? 5 : 6; }
 constexpr int vjp_chunk(int mode) { return 256 * vjp_j(mode); }
 // Forward sweep: FWD_J band entries per lane, FWD_CHUNK entries per block.
 constexpr int FWD_J = 3;

@@ -1398,10 +1398,11 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
   }
 }
 
-// At most 96 VGPRs in volume mode: 5 waves per SIMD (one more register
-// granule would leave 4).
+// At most 96 VGPRs in volume mode (5 waves per SIMD; one more register
+// granule would leave 4) and 128 in surface mode (4 waves, with 6 entries per
+// lane: 8 entries needed about 150 registers, 3 waves, and ran 4% slower).
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3) k_vjp_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb,
+__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 4) k_vjp_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb,
                                                          const float4* __restrict__ erec, int64_t nE, int n_sub,
                                                          float* __restrict__ part) {
   __shared__ VjpLds<MODE> L;
@@ -1477,9 +1478,9 @@ __global__ void __launch_bounds__(SWEEP_T, 7) k_batch_fwd(const SweepItem* __res
 }
 
 // The item loop around the tile must not cost occupancy: at least as many
-// waves per SIMD as the single-request gradient sweep (5 volume, 3 surface).
+// waves per SIMD as the single-request gradient sweep (5 volume, 4 surface).
 template <int MODE>
-__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 3)
+__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 4)
     k_batch_vjp(const SweepItem* __restrict__ items, int n_items, const SweepReq* __restrict__ reqs,
                 int* __restrict__ counter) {
   constexpr int NC = MODE == 0 ? 3 : 10;
