@@ -1259,10 +1259,14 @@ __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, i
 template <int MODE>
 __device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3 : 10], int tt, int lane, int w,
                                                 VjpLds<MODE>& L) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
+  float v[NC];
 #pragma unroll
-  for (int ch = 0; ch < (MODE == 0 ? 3 : 10); ++ch) {
-    const float v = row_sum(acc[ch]);
-    if ((lane & 15) == 0) L.tot[w][lane >> 4][tt][ch] = v;
+  for (int ch = 0; ch < NC; ++ch) v[ch] = row_sum(acc[ch]);
+  // one store block, so the channels go out as wide LDS writes
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) L.tot[w][lane >> 4][tt][ch] = v[ch];
   }
 }
 
