@@ -221,7 +221,10 @@ void oracle_mesh_ft(int mode, const double* V, int nv, const int* F, int nt, con
 }
 
 /* Vertex gradient of L = sum_k Re[ W_k * u(xi_k) ] where u is
- *   mode 0: chi(xi);   mode 1: the normalised surface transform of Eq. 5.
+ *   mode 0: chi(xi);   mode 1: the normalised surface transform of Eq. 5;
+ *   mode 2: the unnormalised surface transform sum_T 2 A_T f_T (Eq. 9 alone,
+ *           the triangle terms of Eq. 6 without the 1/|Lambda| factor and
+ *           without the normalisation term).
  * For mode 1 the normalisation term of Eq. 6 needs u at every xi_k, which the
  * routine evaluates itself.  With density weights (tri_w, NULL for 1) the
  * transforms are the weighted sums of oracle_mesh_ft and mode 1 divides by
@@ -265,6 +268,22 @@ void oracle_mesh_ft_vjp(int mode, const double* V, int nv, const int* F, int nt,
             double r = G[t].wt * creal(W * (I * B[p]));
             int v = F[3 * t + p];
             for (int j = 0; j < 3; ++j) a[3 * v + j] += r * G[t].n[j];
+          }
+        }
+      } else if (mode == 2) {
+        /* Eq. 9: du_T/dv_p = -f_T w_p + 2 A_T df_T/dv_p, summed over the triangles. */
+        for (int t = 0; t < nt; ++t) {
+          double y[3];
+          cplx B[3];
+          phases(&G[t], x, y);
+          const cplx f = tri_f(y);
+          tri_dfdv(y, B);
+          for (int p = 0; p < 3; ++p) {
+            int v = F[3 * t + p];
+            for (int j = 0; j < 3; ++j) {
+              cplx duT = -f * G[t].w[p][j] + G[t].twoA * x[j] * B[p];
+              a[3 * v + j] += G[t].wt * creal(W * duT);
+            }
           }
         }
       } else {

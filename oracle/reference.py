@@ -38,6 +38,10 @@ SRC = HERE / "meshft_oracle.c"
 LIB = HERE / "_meshft_oracle.so"
 
 VOLUME, SURFACE = 0, 1
+# Gradient mode of mesh_ft_vjp_raw only: the unnormalised surface transform
+# sum_T 2 A_T f_T (Eq. 9 summed over triangles, no 1/|Lambda|, no Eq. 6
+# normalisation term).
+SURFACE_RAW = 2
 TWO_PI = 2.0 * np.pi
 
 
@@ -164,8 +168,10 @@ def cone_volume_ft(V, F, xi, c=None) -> np.ndarray:
 
 def mesh_ft_vjp_raw(V, F, xi, W, mode: int, tri_w=None) -> np.ndarray:
     """Gradient with respect to V of sum_k Re[W_k u(xi_k)], where u is the
-    indicator transform (VOLUME) or the normalised surface transform (SURFACE),
-    both weighted by ``tri_w`` when given."""
+    indicator transform (VOLUME), the normalised surface transform (SURFACE)
+    or the unnormalised one, sum_T 2 A_T f_T (SURFACE_RAW), all weighted by
+    ``tri_w`` when given.  VOLUME and SURFACE_RAW are sums of per-triangle
+    terms, so on a subset of the triangles they give those triangles' share."""
     V, F = _d(V), _i(F)
     xi = _d(xi).reshape(-1, 3)
     W = np.asarray(W, dtype=np.complex128).reshape(-1)
@@ -184,6 +190,25 @@ def surface_area(V, F, tri_w=None) -> float:
     n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
     a = 0.5 * np.linalg.norm(n, axis=1)
     return float(a.sum() if tri_w is None else (a * _d(tri_w)).sum())
+
+
+def surface_area_grad(V, F, tri_w=None) -> np.ndarray:
+    """d|Lambda|/dV [n_v, 3]: each triangle adds dA_T/dv_p = -w_p/2 (Sec. 4.1.2,
+    w_p = e_p x N_T with e_p = v_{p-1} - v_{p+1}), times w_T if weighted;
+    zero-area triangles add nothing."""
+    V = _d(V)
+    F = np.asarray(F, dtype=np.int64)
+    P = V[F]                                   # [nt, 3 vertices, 3]
+    n = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    two_a = np.linalg.norm(n, axis=1)
+    N = np.divide(n, two_a[:, None], out=np.zeros_like(n), where=two_a[:, None] > 0)
+    wt = np.ones(len(F)) if tri_w is None else _d(tri_w).reshape(-1)
+    out = np.zeros_like(V)
+    for p in range(3):
+        e = P[:, (p + 2) % 3] - P[:, (p + 1) % 3]
+        w = np.cross(e, N)
+        np.add.at(out, F[:, p], -0.5 * w * wt[:, None])
+    return out
 
 
 # ---------------------------------------------------------------- frequencies
@@ -266,11 +291,46 @@ def spectrum(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None, tri_
     return h * u * band, (xi, h, band, u)
 
 
-def render(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None, tri_w=None) -> np.ndarray:
-    """Image on the grid: Re(ifftn(I_hat)) / (Dx Dy Dz)."""
-    Ihat, _ = spectrum(V, F, grid, sigma6, mode, band_sigma6, tri_w)
+def image_of_spectrum(Ihat, grid) -> np.ndarray:
+    """Re(ifftn(I_hat)) / (Dx Dy Dz) for a full-grid spectrum."""
     dvol = float(grid.spacing[0]) * float(grid.spacing[1]) * float(grid.spacing[2])
     return np.real(np.fft.ifftn(Ihat)) / dvol
+
+
+def render(V, F, grid, sigma6, mode: int | None = None, band_sigma6=None, tri_w=None, return_spectrum=False):
+    """Image on the grid: Re(ifftn(I_hat)) / (Dx Dy Dz).  With
+    ``return_spectrum``, also the second result of ``spectrum`` (full-grid
+    xi, h, band and the mesh transform u, zero off the band)."""
+    Ihat, parts = spectrum(V, F, grid, sigma6, mode, band_sigma6, tri_w)
+    img = image_of_spectrum(Ihat, grid)
+    return (img, parts) if return_spectrum else img
+
+
+def vjp_band(grid, sigma6, dL_dI):
+    """The band quantities of the gradient for a given dL/dI: full-grid band
+    mask, and on the band xi, h, G = fftn(dL/dI) and the adjoint weights
+    W = conj(G) h / (Lx Ly Lz), so that dL/dtheta = sum_band Re[W du/dtheta]
+    for the mesh transform u (band held fixed)."""
+    xi, h, band = otf_and_band(grid, sigma6)
+    G = np.fft.fftn(np.asarray(dL_dI, dtype=np.float64))
+    LV = float(np.prod(lengths(grid)))
+    xb, hb, Gb = xi[band], h[band], G[band]
+    W = np.conj(Gb) * hb / LV
+    return band, xb, hb, Gb, W
+
+
+def psf_grad(grid, xb, hb, Gb, ub) -> np.ndarray:
+    """dL/dSigma [6] from the band quantities of ``vjp_band`` and the mesh
+    transform ``ub`` on the band: dh/dSigma_ab = -xi_a xi_b h / 2 (times 2 for
+    an off-diagonal entry, which stands for both symmetric positions)."""
+    LV = float(np.prod(lengths(grid)))
+    base = np.real(np.conj(Gb) * ub * hb) / LV
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    dS = np.zeros(6)
+    for i, (a, b) in enumerate(pairs):
+        fac = -0.5 * xb[:, a] * xb[:, b] * (1.0 if a == b else 2.0)
+        dS[i] = float(np.sum(base * fac))
+    return dS
 
 
 def render_vjp(V, F, grid, sigma6, dL_dI, mode: int | None = None, tri_w=None):
@@ -281,21 +341,11 @@ def render_vjp(V, F, grid, sigma6, dL_dI, mode: int | None = None, tri_w=None):
     (xx, yy, zz, xy, xz, yz); an off-diagonal entry stands for both symmetric
     positions of Sigma."""
     mode = grid.mode if mode is None else mode
-    xi, h, band = otf_and_band(grid, sigma6)
-    G = np.fft.fftn(np.asarray(dL_dI, dtype=np.float64))
-    LV = float(np.prod(lengths(grid)))
-    xb, hb, Gb = xi[band], h[band], G[band]
-    W = np.conj(Gb) * hb / LV
+    band, xb, hb, Gb, W = vjp_band(grid, sigma6, dL_dI)
     Vr = _d(V) - np.asarray(grid.origin, dtype=np.float64)
     dV = mesh_ft_vjp_raw(Vr, F, xb, W, mode, tri_w) if band.any() else np.zeros((len(V), 3))
     u = mesh_transform(V, F, xb, grid, mode, tri_w) if band.any() else np.zeros(0, complex)
-    base = np.real(np.conj(Gb) * u * hb) / LV
-    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
-    dS = np.zeros(6)
-    for i, (a, b) in enumerate(pairs):
-        fac = -0.5 * xb[:, a] * xb[:, b] * (1.0 if a == b else 2.0)
-        dS[i] = float(np.sum(base * fac))
-    return dV, dS
+    return dV, psf_grad(grid, xb, hb, Gb, u)
 
 
 # ------------------------------------------------------- tabulated OTF

@@ -323,8 +323,9 @@ def test_volume_supersampled_voxelisation(ref):
 
 
 # ----------------------------------------------------------------- gradients
-@pytest.mark.parametrize("mode", [VOLUME, SURFACE])
+@pytest.mark.parametrize("mode", [VOLUME, SURFACE, 2])
 def test_vertex_gradient_matches_finite_differences(ref, mode):
+    """Mode 2 is the unnormalised surface transform sum_T 2 A_T f_T."""
     V, F = _deformed(1, seed=2, R=2.0)
     rng = np.random.default_rng(11)
     xi = rng.normal(size=(12, 3)) * 1.2
@@ -332,7 +333,7 @@ def test_vertex_gradient_matches_finite_differences(ref, mode):
     W = rng.normal(size=12) + 1j * rng.normal(size=12)
 
     def loss(Vx):
-        u = ref.mesh_ft_raw(Vx, F, xi, mode)
+        u = ref.mesh_ft_raw(Vx, F, xi, VOLUME if mode == VOLUME else SURFACE)
         if mode == SURFACE:
             u = u / ref.surface_area(Vx, F)
         return float(np.real(np.sum(W * u)))
@@ -346,6 +347,51 @@ def test_vertex_gradient_matches_finite_differences(ref, mode):
             Vm[vi, j] -= h
             fd = (loss(Vp) - loss(Vm)) / (2 * h)
             assert abs(g[vi, j] - fd) < 1e-6 * (np.abs(g).max()), (vi, j, g[vi, j], fd)
+
+
+def test_surface_area_gradient_matches_finite_differences(ref):
+    """d|Lambda|/dV (with and without density weights, and with a zero-area
+    triangle, which adds nothing) against central differences of the area."""
+    V, F = _deformed(1, seed=4)
+    n = len(V)
+    V = np.concatenate([V, V[F[0, 0]][None], V[F[0, 0]][None] + [0.3, 0.0, 0.0]])
+    F = np.concatenate([F, [[F[0, 0], n, n + 1]]])   # collinear: zero area
+    wts = np.random.default_rng(3).uniform(0.5, 1.5, len(F))
+    for tw in (None, wts):
+        g = ref.surface_area_grad(V, F, tw)
+        h = 1e-6
+        for vi in [0, 3, 11, 29, n]:
+            for j in range(3):
+                Vp, Vm = V.copy(), V.copy()
+                Vp[vi, j] += h
+                Vm[vi, j] -= h
+                fd = (ref.surface_area(Vp, F[:-1], None if tw is None else tw[:-1])
+                      - ref.surface_area(Vm, F[:-1], None if tw is None else tw[:-1])) / (2 * h)
+                assert abs(g[vi, j] - fd) < 1e-7 * np.abs(g).max(), (vi, j, g[vi, j], fd)
+    # the mesh is closed: moving it rigidly keeps the area, so the gradient sums to zero
+    assert np.abs(ref.surface_area_grad(V[:n], F[:-1]).sum(axis=0)).max() < 1e-12 * ref.surface_area(V[:n], F[:-1])
+
+
+def test_surface_gradient_assembles_from_triangle_terms(ref):
+    """Eq. 6 split into its two parts: on every vertex, the normalised
+    surface gradient equals (raw triangle terms of the triangles around the
+    vertex - s d|Lambda|/dv) / |Lambda| with the global scalar
+    s = sum_k Re[W_k u_k] of the normalised transform u.  This is how a
+    large mesh's gradient is checked at a few vertices."""
+    V, F = _deformed(1, seed=7, R=2.5)
+    rng = np.random.default_rng(17)
+    xi = rng.normal(size=(20, 3)) * 1.1
+    W = rng.normal(size=20) + 1j * rng.normal(size=20)
+    full = ref.mesh_ft_vjp_raw(V, F, xi, W, SURFACE)
+    area = ref.surface_area(V, F)
+    u = ref.mesh_ft_raw(V, F, xi, SURFACE) / area
+    s = float(np.real(np.sum(W * u)))
+    dA = ref.surface_area_grad(V, F)
+    for v in [0, 9, 23]:
+        tris = np.nonzero((F == v).any(axis=1))[0]
+        local = ref.mesh_ft_vjp_raw(V, F[tris], xi, W, 2)[v]
+        got = (local - s * dA[v]) / area
+        assert np.abs(got - full[v]).max() < 1e-12 * np.abs(full).max(), (v, got, full[v])
 
 
 def test_volume_gradient_at_zero_frequency_is_normal_sum(ref):
