@@ -256,33 +256,14 @@ def test_vjp_random_cotangent(dm, handle, ref, name, mode):
     assert rel_l2(img.cpu().numpy(), want) < IMG_TOL
 
 
-def test_cfg3_volume_gradient_at_sampled_vertices(dm, handle, ref):
-    """The benchmark's full-size launch (cfg3, 5120 triangles x 549,888 band
-    entries, cotangent N(0,1) seed 0): the gradients of 12 sampled vertices
-    against the oracle evaluated on the triangles around them.  The adjoint
-    weights do not depend on the mesh and each triangle adds its own terms, so
-    these triangles alone fix those vertices' gradients."""
-    say("vjp cfg3 sampled vertices")
-    c = configs.cfg3(VOLUME)
-    V, F, g, S = prepared(c, VOLUME)
-    G = np.random.default_rng(0).standard_normal(g.n).astype(np.float32)
-    topo = handle.topology(F, n_verts=len(V))
-    dv, ds, _ = dm.render_vjp(handle, dev(V), topo, S, g, dev(G), want_sigma=False)
-    vs = np.random.default_rng(21).choice(len(V), 12, replace=False)
-    tris = np.nonzero(np.isin(F, vs).any(axis=1))[0]
-    dvw, _ = ref.render_vjp(V.astype(np.float64), F[tris], g, S, G.astype(np.float64))
-    err = rel_l2(dv.cpu().numpy()[vs], dvw[vs])
-    say("  rel err", err)
-    assert err < GRAD_TOL, err
-
-
 def test_largest_serving_shape_at_sampled_outputs(dm, handle, ref):
     """The largest request of the serving workload: a deformed geodesic
     sphere of 40,500 triangles in the 256x256x128 grid (unit voxels,
     sigma_xy = 1, band about 1.5M entries, |k| up to 128, so vertex phases
     reach about 40 revolutions), in the launch configuration of a single call.
-    Checked on what the oracle can evaluate at this size: the mesh transform
-    at 300 sampled frequencies (the extreme ones included), the image's
+    Checked on what the oracle can evaluate at this size: the band spectrum
+    of dm_render at 600 sampled band entries (the extreme frequencies
+    included), the mesh transform at 300 sampled frequencies, the image's
     integral (the k = 0 term, the enclosed volume) and the gradients of 4
     sampled vertices (from the triangles around them)."""
     import torch
@@ -291,6 +272,18 @@ def test_largest_serving_shape_at_sampled_outputs(dm, handle, ref):
     V, F, g, S = prepared(c, VOLUME)
     say("  triangles", len(F), "band", dm.band_size(handle, g, S))
     topo = handle.topology(F, n_verts=len(V))
+    _, spec = dm.render(handle, dev(V), topo, S, g, spectrum=True)
+    kb = dm.band_export(handle, g, S)["k"]
+    ext = [int(np.argmax(kb[:, j])) for j in range(3)] + [int(np.argmin(kb[:, j])) for j in range(3)]
+    ext.append(int(np.argmax(np.abs(kb).sum(axis=1))))
+    pick = np.concatenate([ext, np.random.default_rng(15).choice(len(kb), 600, replace=False)])
+    sp = spec.cpu().numpy().astype(np.float64)[pick]
+    got = sp[:, 0] + 1j * sp[:, 1]
+    want = ref.mesh_transform(V.astype(np.float64), F, ref.xi_of_k(kb[pick], g), g, VOLUME)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say("  band spectrum: max err / scale", err, "rel l2", rel_l2(got, want))
+    assert err < 2e-6 and rel_l2(got, want) < IMG_TOL
+    del spec
     K = _k_samples(g, np.random.default_rng(12))
     got = dm.mesh_transform(handle, dev(V), topo, g, dev(K)).cpu().numpy().astype(np.complex128)
     want = ref.mesh_transform(V.astype(np.float64), F, ref.xi_of_k(K, g), g, VOLUME)
