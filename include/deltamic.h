@@ -234,6 +234,31 @@ dm_status dm_render_vjp(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, co
 dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev,
                             int64_t n, float* out_dev, void* stream);
 
+/* Size of the fixed device scratch of dm_mesh_transform_noalloc, per GPU. */
+#define DM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* dm_mesh_transform without any allocation, for callers that cannot allocate
+ * device memory: work enqueued under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, same result up to the
+ * order of float32 additions (bitwise the same whenever dm_mesh_transform's
+ * triangle chunking fits the scratch).  The call allocates nothing: no
+ * hipMalloc or hipFree, no library routine that allocates, no growth of the
+ * handle's workspace; its intermediates (triangle records, mesh totals, the
+ * frequency table and the per-chunk partial sums) live in a fixed array of
+ * DM_NOALLOC_SCRATCH_BYTES bytes in the library's code object, one per GPU,
+ * whose address dm_create resolves for its device.  With the triangles in c
+ * chunks it needs 64 n_faces + 16 n + 8 n c bytes plus at most 20 KiB; when
+ * dm_mesh_transform's chunking does not fit, fewer chunks are used (down to
+ * one), and a request that does not fit with one chunk returns DM_ERR_BUDGET
+ * before anything is enqueued.  Every call on a
+ * GPU shares that GPU's scratch and leaves its contents behind (nothing in it
+ * needs to start at zero): calls on one handle are ordered, but calls that
+ * overlap on one GPU through different handles, or from several threads,
+ * race on the scratch and give wrong results.  Kernel timing
+ * (dm_timing_enable) does not cover this call. */
+dm_status dm_mesh_transform_noalloc(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev,
+                                    int64_t n, float* out_dev, void* stream);
+
 /* ----------------------------------------------------------------- batch */
 
 /* One request of a batch: the forward render and/or gradient of one mesh on

@@ -115,6 +115,7 @@ def _load():
         "dm_render_vjp": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CPsf), ctypes.POINTER(CGrid), vp, vp, vp, vp,
                           vp, vp],
         "dm_mesh_transform": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CGrid), vp, i64, vp, vp],
+        "dm_mesh_transform_noalloc": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CGrid), vp, i64, vp, vp],
         "dm_timing_enable": [vp, ctypes.c_int],
         "dm_timing_read": [vp, ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime),
                            ctypes.c_int],
@@ -546,18 +547,26 @@ class Server:
         return {k: getattr(st, k) for k, _ in CServerStats._fields_}
 
 
-def mesh_transform(h: Handle, verts, topo: Topology, grid, k):
-    """u_hat(2 pi k / L) as complex64 [n] for integer frequencies k [n, 3]."""
+def mesh_transform(h: Handle, verts, topo: Topology, grid, k, out=None, noalloc: bool = False):
+    """u_hat(2 pi k / L) as complex64 [n] for integer frequencies k [n, 3].
+
+    out: optional float32 [n, 2] device tensor to write into.  noalloc: call
+    dm_mesh_transform_noalloc, which works in the library's fixed scratch and
+    allocates nothing (pass `out` and a device int32 `k` to keep the whole
+    call allocation-free)."""
     torch = _torch()
     verts = _dev_tensor(verts, torch.float32, 3, "verts")
     if not isinstance(k, torch.Tensor):
         k = torch.as_tensor(np.asarray(k, dtype=np.int32))
     k = k.to(device=verts.device, dtype=torch.int32).contiguous()
-    out = torch.empty((k.shape[0], 2), dtype=torch.float32, device=verts.device)
+    if out is None:
+        out = torch.empty((k.shape[0], 2), dtype=torch.float32, device=verts.device)
+    elif tuple(out.shape) != (k.shape[0], 2) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of shape [n, 2]")
     g, m = _grid(grid), _mesh(verts, topo)
-    _check(_load().dm_mesh_transform(h.ptr, ctypes.byref(m), ctypes.byref(g), ctypes.c_void_p(k.data_ptr()),
-                                     int(k.shape[0]), ctypes.c_void_p(out.data_ptr()), _stream(h.device)),
-           "dm_mesh_transform")
+    name = "dm_mesh_transform_noalloc" if noalloc else "dm_mesh_transform"
+    _check(getattr(_load(), name)(h.ptr, ctypes.byref(m), ctypes.byref(g), ctypes.c_void_p(k.data_ptr()),
+                                  int(k.shape[0]), ctypes.c_void_p(out.data_ptr()), _stream(h.device)), name)
     return torch.view_as_complex(out)
 
 

@@ -11,8 +11,9 @@ TMP="$(mktemp -d)"
 trap 'rm -rf "$TMP"' EXIT
 "$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_kernels.hip" -o "$TMP/dm_kernels.o"
 "$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_precond.hip" -o "$TMP/dm_precond.o"
+"$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_scratch.hip" -o "$TMP/dm_scratch.o"
 "$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_host.cpp" -o "$TMP/dm_host.o"
-"$ROCM/bin/hipcc" -shared --offload-arch=gfx950 -o "$OUT.tmp" "$TMP/dm_kernels.o" "$TMP/dm_precond.o" "$TMP/dm_host.o" \
+"$ROCM/bin/hipcc" -shared --offload-arch=gfx950 -o "$OUT.tmp" "$TMP/dm_kernels.o" "$TMP/dm_precond.o" "$TMP/dm_scratch.o" "$TMP/dm_host.o" \
   -L"$ROCM/lib" -lrocfft -Wl,-rpath,"$ROCM/lib"
 mv -f "$OUT.tmp" "$OUT"
 echo "built $OUT"

@@ -1039,6 +1039,8 @@ dm_status dm_create(dm_handle** out, int device, size_t hbm_budget_bytes) {
   h->device = device;
   h->budget = hbm_budget_bytes;
   HIP_TRY(hipEventCreateWithFlags(&h->last_ev, hipEventDisableTiming));
+  // the allocation-free entry point's scratch: its address on this device
+  HIP_TRY(scratch_init(device));
   *out = h.release();
   return DM_OK;
 }
@@ -1498,6 +1500,62 @@ dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g,
   SweepTimer tm(h, s, 0, (double)n * nt);
   HIP_TRY(launch_fwd_lanes(mode, kf, n, rec, nt, sp.per_chunk, sp.n_chunks, part, s));
   tm.done();
+  HIP_TRY(launch_points_finalize(mode, gc, kf, n, part, sp.n_chunks, info, reinterpret_cast<float2*>(out_dev), s));
+  return end_call(h, s);
+}
+
+dm_status dm_mesh_transform_noalloc(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev,
+                                    int64_t n, float* out_dev, void* stream) {
+  g_err.clear();
+  if (!h) return fail(DM_ERR_ARG, "NULL handle");
+  DM_TRY(check_grid(g));
+  DM_TRY(check_mesh(mesh, g->mode));
+  if (n < 0 || (n > 0 && (!k_dev || !out_dev))) return fail(DM_ERR_ARG, "bad frequency list");
+  if (n >= ((int64_t)1 << 31)) return fail(DM_ERR_ARG, "too many frequencies");
+  if (n == 0) return DM_OK;
+  DeviceGuard dg(h->device);
+  char* base = static_cast<char*>(scratch_ptr(h->device));
+  if (!base) return fail(DM_ERR_DEVICE, "scratch of device %d not resolved", h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int mode = g->mode;
+  const GridC gc = make_gridc(g);
+  const int nt = mesh->topo->nt;
+  // the same triangle chunking as dm_mesh_transform when it fits, else fewer chunks
+  SweepPlan sp = plan_fwd(n, nt);
+  const int prep_blocks = mesh_prep_blocks(nt);
+  size_t o_rec = 0, o_info = 0, o_ptmp = 0, o_kf = 0, o_part = 0, need = 0;
+  for (;;) {
+    Carver cv;
+    o_rec = cv.take<float>((size_t)std::max(nt, 1) * TRI_REC);
+    o_info = cv.take<MeshInfo>(1);
+    o_ptmp = cv.take<double>(2 * (size_t)prep_blocks);
+    o_kf = cv.take<float4>(n);
+    o_part = cv.take<float2>((size_t)sp.n_chunks * n);
+    need = cv.off;
+    if (need <= DM_NOALLOC_SCRATCH_BYTES || sp.n_chunks == 1) break;
+    const int64_t fixed = (int64_t)o_part;
+    const int64_t fit = ((int64_t)DM_NOALLOC_SCRATCH_BYTES - fixed) / (8 * n);
+    const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(sp.n_chunks - 1, fit));
+    sp.per_chunk = std::max(1, (nt + chunks - 1) / chunks);
+    sp.n_chunks = std::max(1, (nt + sp.per_chunk - 1) / sp.per_chunk);
+  }
+  if (need > DM_NOALLOC_SCRATCH_BYTES)
+    return fail(DM_ERR_BUDGET, "%d triangles and %lld frequencies need %zu bytes of scratch; it holds %zu", nt,
+                (long long)n, need, (size_t)DM_NOALLOC_SCRATCH_BYTES);
+  DM_TRY(begin_call(h, s));
+  if (nt == 0) {
+    DM_TRY(zero_fill(out_dev, 2 * n, s));
+    return end_call(h, s);
+  }
+  float* rec = reinterpret_cast<float*>(base + o_rec);
+  MeshInfo* info = reinterpret_cast<MeshInfo*>(base + o_info);
+  HIP_TRY(launch_mesh_prep(mode, gc, mesh->verts_dev, mesh->n_verts, mesh->topo->faces, mesh->topo->flags,
+                           mesh->topo->weights, nt, rec, info, reinterpret_cast<double*>(base + o_ptmp), prep_blocks,
+                           s));
+  float4* kf = reinterpret_cast<float4*>(base + o_kf);
+  HIP_TRY(launch_points_prepare(gc, k_dev, n, kf, s));
+  float2* part = reinterpret_cast<float2*>(base + o_part);
+  HIP_TRY(launch_fwd_lanes(mode, kf, n, rec, nt, sp.per_chunk, sp.n_chunks, part, s));
   HIP_TRY(launch_points_finalize(mode, gc, kf, n, part, sp.n_chunks, info, reinterpret_cast<float2*>(out_dev), s));
   return end_call(h, s);
 }

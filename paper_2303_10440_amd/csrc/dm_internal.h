@@ -167,4 +167,11 @@ hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* 
                                  float lam, const float* g, float* out, float* ws, int max_iter, float tol,
                                  float* info, hipStream_t s);
 
+// Fixed scratch of the allocation-free entry point (dm_scratch.hip):
+// scratch_init resolves its device address for `device`, which must be the
+// current device (once per device; later calls return at once);
+// scratch_ptr returns that address, or nullptr before scratch_init.
+hipError_t scratch_init(int device);
+void* scratch_ptr(int device);
+
 }  // namespace dm
