@@ -9,7 +9,8 @@ image, FFT of dL/dI, adjoint weights and PSF gradient, gradient sweep and the
 per-vertex reduction.  Inputs are resident in HBM before timing starts.
 
 value = triangles x band entries / step time (each frequency-triangle pair is
-evaluated once by the forward sweep and once by the gradient sweep per step).
+evaluated once forward and once for the gradient per step; with dL/dI given
+and the image wanted, dm_render_vjp does both in one fused sweep).
 
 Prints ONE JSON line.  Synthetic data (seeded); no dataset.
 """
@@ -45,6 +46,9 @@ ALG = {
     "vjp_volume": {"flops": 50.0, "sin": 3, "cos": 3, "rcp": 3},
     "vjp_surface": {"flops": 80.0, "sin": 3, "cos": 3, "rcp": 3},
 }
+# The fused sweep evaluates both per pair: its algorithmic work is the sum.
+for _m in ("volume", "surface"):
+    ALG["fused_" + _m] = {k: ALG["fwd"][k] + ALG["vjp_" + _m][k] for k in ALG["fwd"]}
 
 
 # HBM traffic of the dominant kernel from two rocprofv3 --pmc passes
@@ -53,13 +57,14 @@ ALG = {
 # known size.  Valid only for the kernel source it was measured on: if the
 # hash of the kernel file differs, the benchmark reports traffic as null.
 TRAFFIC = {
-    "kernel": "k_vjp_lanes<0>",
-    "source_sha256": "bc7064e88ec0a71128489e036abfa0a0e6af47eab9e2cfcc30063b94e241b305",
-    # FETCH_SIZE 2,532,189 KiB x 2.000 (a 256 MiB copy reads 131,089 KiB) and
-    # WRITE_SIZE 14,331 KiB x 1.000 (the copy writes 262,144 KiB), per launch
-    "read_bytes": 2532188.8 * 1024 * 2.0,
-    "write_bytes": 14331.1 * 1024 * 1.0,
-    "profile": "profiles/k_vjp_lanes_cfg3_volume.md",
+    "kernel": "k_fused_lanes<0>",
+    "source_sha256": "f9e5632e57911b9ecd4e985f9575de666054373d9bfca2e4f55a9a4c56955354",
+    # FETCH_SIZE 1,362,511 KiB x 2.000 (a 256 MiB copy reads 131,090 KiB) and
+    # WRITE_SIZE 205,603 KiB x 1.000 (the copy writes 262,144 KiB), per launch
+    # (mean of three launches each)
+    "read_bytes": 1362510.6 * 1024 * 2.0,
+    "write_bytes": 205602.9 * 1024 * 1.0,
+    "profile": "profiles/k_fused_lanes_cfg3_volume.md",
 }
 TRAFFIC["bytes_per_launch"] = TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
 
@@ -227,10 +232,25 @@ def bench_batch(dm, h, reps: int = 2) -> dict:
     e2.record(s)
     torch.cuda.synchronize()
     tb, tl = e0.elapsed_time(e1) / reps, e1.elapsed_time(e2) / reps
+    # sweep-kernel pair rates: the persistent launch over all 64 cells against
+    # the single calls' fused sweeps (launch events around each)
+    h.timing(True)
+    h.timing_read(reset=True)
+    dm.batch_run(h, reqs)
+    torch.cuda.synchronize()
+    kb = h.timing_read(reset=True)["batch"]
+    for r in reqs:
+        dm.render_vjp(h, *r, want_image=True)
+    torch.cuda.synchronize()
+    kf = h.timing_read(reset=True)["fused"]
+    h.timing(False)
     return {"workload": "64 deformed cells, n_t log-uniform [1k, 20k], grids {64^3, 96^3, 128x128x64}, "
-                        "sigma_xy = 1, sigma_z ~ U[1.5, 3] voxels, forward + gradient",
+                        "sigma_xy = 1, sigma_z ~ U[1.5, 3] voxels, forward + gradient, all in one persistent "
+                        "launch per density",
             "pairs": pairs, "batched_ms": tb, "looped_ms": tl, "batched_pairs_per_s": pairs / (tb * 1e-3),
-            "looped_pairs_per_s": pairs / (tl * 1e-3), "speedup": tl / tb, "max_image_rel_diff": worst}
+            "looped_pairs_per_s": pairs / (tl * 1e-3), "speedup": tl / tb, "max_image_rel_diff": worst,
+            "persistent_sweep": {"launches": kb[0], "ms": kb[1], "pairs_per_s": kb[2] / (kb[1] * 1e-3)},
+            "single_call_sweeps": {"launches": kf[0], "ms": kf[1], "pairs_per_s": kf[2] / (kf[1] * 1e-3)}}
 
 
 def bench_fit(dm, h, case, mode, shape_steps: int = 10, psf_steps: int = 4) -> dict:
@@ -388,11 +408,14 @@ def bench_smooth(dm, reps: int = 20) -> dict:
         t_cpu = time.perf_counter() - t0
         err = float(np.linalg.norm(o.cpu().numpy() - want) / np.linalg.norm(want))
         its = info["iters"][0] + info["iters"][1]
-        out.append({"mesh": name, "n_verts": nv, "ms": ms, "cg_iterations": list(info["iters"]),
+        out.append({"mesh": name, "n_verts": nv, "ms": ms,
+                    "solver": "CG, one workgroup" if nv <= 3072 else "Chebyshev, one launch per step",
+                    "iterations": list(info["iters"]), "residuals": list(info["residual"]),
                     "us_per_iteration": ms * 1e3 / max(its, 1), "rel_err_vs_oracle": err,
                     "oracle_ms": t_cpu * 1e3})
-    return {"workload": "(I + 50 L)^{-2} g, L the edge-graph Laplacian, random g, CG to relative residual 1e-6 "
-                        "per solve (one workgroup, Jacobi preconditioner)", "cases": out}
+    return {"workload": "(I + 50 L)^{-2} g, L the edge-graph Laplacian, random g, relative residual 1e-6 per "
+                        "solve: Jacobi-preconditioned CG in one workgroup up to 3072 vertices, Chebyshev "
+                        "iteration with a priori step counts above", "cases": out}
 
 
 def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_inflight: int, pool: int = 32,
@@ -530,24 +553,26 @@ def main() -> int:
     ms_step = total_ms / args.steps
     lat = np.array([a.elapsed_time(b) for a, b in evs])
 
-    fwd_launch, fwd_ms, fwd_pairs = kt["fwd"]
-    vjp_launch, vjp_ms, vjp_pairs = kt["vjp"]
-    vkind = "vjp_volume" if mode == configs.VOLUME else "vjp_surface"
-    sweeps = {
-        "fwd": {"avg_ms": fwd_ms / max(fwd_launch, 1), "pairs_per_s": fwd_pairs / (fwd_ms * 1e-3),
-                "flop_eq_per_pair": flop_eq("fwd", rates),
-                "frac": fwd_pairs / (fwd_ms * 1e-3) * flop_eq("fwd", rates) / (PEAK_TFLOPS * 1e12)},
-        "vjp": {"avg_ms": vjp_ms / max(vjp_launch, 1), "pairs_per_s": vjp_pairs / (vjp_ms * 1e-3),
-                "flop_eq_per_pair": flop_eq(vkind, rates),
-                "frac": vjp_pairs / (vjp_ms * 1e-3) * flop_eq(vkind, rates) / (PEAK_TFLOPS * 1e12)},
-    }
-    dom = "fwd" if fwd_ms >= vjp_ms else "vjp"
-    dkind = "fwd" if dom == "fwd" else vkind
-    launches = fwd_launch if dom == "fwd" else vjp_launch
-    dms = (fwd_ms if dom == "fwd" else vjp_ms) / max(launches, 1)
-    per_launch_pairs = (fwd_pairs if dom == "fwd" else vjp_pairs) / max(launches, 1)
+    msuf = "volume" if mode == configs.VOLUME else "surface"
+    kinds = {"fwd": ("k_fwd_lanes", "fwd"), "vjp": ("k_vjp_lanes", "vjp_" + msuf),
+             "fused": ("k_fused_lanes", "fused_" + msuf)}
+    sweeps = {}
+    for key, (kn, alg) in kinds.items():
+        n_l, ms_sum, prs = kt[key]
+        if n_l == 0:
+            continue
+        sweeps[key] = {"kernel": kn + ("<0>" if mode == configs.VOLUME else "<1>"), "launches_per_step": n_l / args.steps,
+                       "avg_ms": ms_sum / n_l, "pairs_per_s": prs / (ms_sum * 1e-3),
+                       "flop_eq_per_pair": flop_eq(alg, rates),
+                       "frac": prs / (ms_sum * 1e-3) * flop_eq(alg, rates) / (PEAK_TFLOPS * 1e12)}
+    # the dominant kernel: the sweep with the largest share of the step
+    dom = max(sweeps, key=lambda k: kt[k][1])
+    dkind = kinds[dom][1]
+    launches, dms_sum, dpairs = kt[dom]
+    dms = dms_sum / launches
+    per_launch_pairs = dpairs / launches
     achieved = per_launch_pairs * flop_eq(dkind, rates) / (dms * 1e-3) / 1e12
-    kname = ("k_fwd_lanes" if dom == "fwd" else "k_vjp_lanes") + ("<0>" if mode == configs.VOLUME else "<1>")
+    kname = sweeps[dom]["kernel"]
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS, "traffic": measured_traffic(kname),
                 "kernel": kname,
@@ -556,6 +581,28 @@ def main() -> int:
                 "algorithmic_per_pair": ALG[dkind],
                 "measured_lane_rates_per_s": {k: rates[k] for k in ("fma",) + TRANS_KINDS},
                 "mix_time_over_sum": rates["mix_over_sum"]}
+
+    # The two sweeps apart, as autograd runs them (dm_render with the band
+    # spectrum, then dm_render_vjp reusing it: forward sweep, then the
+    # gradient sweep alone), timed by the same launch events.
+    n_sep = max(3, min(10, args.steps))
+    h.timing(True)
+    h.timing_read(reset=True)
+    for _ in range(n_sep):
+        _, spec = dm.render(h, V, topo, sigma, g, spectrum=True)
+        dm.render_vjp(h, V, topo, sigma, g, G, spectrum_in=spec)
+    torch.cuda.synchronize()
+    h.timing(False)
+    kt2 = h.timing_read(reset=True)
+    separate = {}
+    for key in ("fwd", "vjp"):
+        kn, alg = kinds[key]
+        n_l, ms_sum, prs = kt2[key]
+        if n_l:
+            separate[key] = {"kernel": kn + ("<0>" if mode == configs.VOLUME else "<1>"), "launches": n_l,
+                             "avg_ms": ms_sum / n_l, "pairs_per_s": prs / (ms_sum * 1e-3),
+                             "flop_eq_per_pair": flop_eq(alg, rates),
+                             "frac": prs / (ms_sum * 1e-3) * flop_eq(alg, rates) / (PEAK_TFLOPS * 1e12)}
 
     out = {
         "metric": METRIC,
@@ -577,6 +624,7 @@ def main() -> int:
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "min": float(lat.min())},
         "sweeps": sweeps,
+        "separate_sweeps": separate,
         "roofline": roofline,
     }
     if args.copy_calibration:

@@ -43,10 +43,13 @@
  *            enqueue their work on it and return; outputs are valid once the
  *            stream has been synchronised.  A handle is not thread-safe:
  *            serialise calls on one handle.
- *  Errors    every entry point returns a dm_status; on failure nothing has
- *            been written to any output and dm_last_error() describes the
- *            cause.  Input checks happen on the host before any work is
- *            enqueued.
+ *  Errors    every entry point returns a dm_status and dm_last_error()
+ *            describes a failure.  Input checks happen on the host before
+ *            any work is enqueued, so a call refused for its arguments, its
+ *            mesh, its PSF or the budget has written nothing.  A device or
+ *            FFT failure after work was enqueued (DM_ERR_DEVICE, DM_ERR_FFT)
+ *            may leave outputs partly written; the handle stays usable and
+ *            its next call is still ordered after the enqueued work.
  *  Results   deterministic: the same inputs give bitwise identical outputs
  *            (all reductions run in a fixed order; no floating-point
  *            atomics).
@@ -218,6 +221,9 @@ dm_status dm_render(dm_handle* h, const dm_mesh* mesh, const dm_psf* psf, const 
  *                 off-diagonal entry stands for both symmetric positions
  *                 of Sigma (may be NULL)
  *   image_dev     optional: the forward image, computed in the same call
+ *                 (with dL_dverts_dev, by the fused sweep that evaluates the
+ *                 forward and gradient sums together: dm_render's image up to
+ *                 the order of float32 additions)
  * The band is held fixed (it depends on Sigma only through the threshold).
  * spectrum_in_dev, if not NULL, is the spectrum dm_render returned for the
  * same mesh, psf and grid, and saves the forward sweep when image_dev is
@@ -296,20 +302,18 @@ dm_status dm_render_otf_vjp(dm_handle* h, const dm_mesh* mesh, const void* otf, 
 
 /* Runs n independent requests of uneven sizes and grids as one batch: the
  * mesh-transform sweeps of all of them (forward, Eq. 5/7-8, and gradient,
- * Eq. 6/9-10) execute in one persistent launch whose workgroups draw work
- * tiles from a shared queue, longest first; the small per-request steps
- * (band, mesh prep, FFTs, adjoint weights, reductions) run around it on the
- * same stream.  A request of at least 5e8 (band entry, triangle) pairs fills
- * the GPU by itself: it runs the sweep launches of dm_render_vjp instead, so
- * its results are bitwise dm_render_vjp's; when a batch holds two or more of
- * these, they alternate between `stream` and a second stream owned by the
- * handle, which starts after the batch's pre-steps on `stream` and which
- * `stream` waits for before anything enqueued on it after this call (work
- * on `stream` sees the whole batch done).  Each request's tiles and
- * summation order depend on that request alone, so its results are bitwise
- * the same whatever else is in the batch (and agree with dm_render_vjp to
- * rounding).  All validation happens before anything is enqueued; on error
- * no output is written. */
+ * Eq. 6/9-10) execute in persistent launches (one per kind of sweep and
+ * density present) whose workgroups draw work tiles of every request from a
+ * shared queue, longest first; the small per-request steps (band, mesh prep,
+ * FFTs, adjoint weights, reductions) run around them on the same stream.  A
+ * request with dL_dimage and both an image (or dL_dsigma) and dL_dverts runs
+ * the tiles of dm_render_vjp's fused sweep, so its outputs are bitwise
+ * dm_render_vjp's; forward-only and gradient-only requests have tiles of
+ * their own (same results as the single calls up to float32 summation
+ * order).  Each request's tiles and summation order depend on that request
+ * alone, so its results are bitwise the same whatever else is in the batch.
+ * All validation happens before anything is enqueued; on error no output is
+ * written. */
 dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* stream);
 
 /* --------------------------------------------------------------- serving */
@@ -378,13 +382,14 @@ dm_status dm_server_stats_read(dm_server* s, dm_server_stats* out);
 /* ------------------------------------------------------------ diagnostics */
 
 /* Kernel timing: while enabled, the handle records HIP events on the call's
- * stream around every launch of the two mesh-transform sweeps (the forward
- * sweep of Eq. 5/7-8 and the gradient sweep of Eq. 6/9-10) and of the batched
- * sweep of dm_batch_run.  dm_timing_read waits for those events and returns,
- * per sweep kind, the number of launches,
- * the summed duration in milliseconds and the summed frequency-triangle
- * pairs they evaluated; reset != 0 clears the counters.  Any output may be
- * NULL. */
+ * stream around every launch of the mesh-transform sweeps (the forward sweep
+ * of Eq. 5/7-8, the gradient sweep of Eq. 6/9-10, the fused sweep that
+ * evaluates both in one pass when dL/dimage is given and the forward result
+ * is wanted too, and the batched sweep of dm_batch_run).  dm_timing_read
+ * waits for those events and returns, per sweep kind, the number of
+ * launches, the summed duration in milliseconds and the summed
+ * frequency-triangle pairs they evaluated (a fused pair counts once);
+ * reset != 0 clears the counters.  Any output may be NULL. */
 typedef struct {
   int64_t launches;
   double ms;
@@ -393,7 +398,7 @@ typedef struct {
 
 dm_status dm_timing_enable(dm_handle* h, int enable);
 dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time* vjp_sweep,
-                         dm_kernel_time* batch_sweep, int reset);
+                         dm_kernel_time* batch_sweep, dm_kernel_time* fused_sweep, int reset);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* dm_last_error(void);

@@ -118,7 +118,7 @@ def _load():
         "dm_mesh_transform_noalloc": [vp, ctypes.POINTER(CMesh), ctypes.POINTER(CGrid), vp, i64, vp, vp],
         "dm_timing_enable": [vp, ctypes.c_int],
         "dm_timing_read": [vp, ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime), ctypes.POINTER(CKernelTime),
-                           ctypes.c_int],
+                           ctypes.POINTER(CKernelTime), ctypes.c_int],
         "dm_batch_run": [vp, i32, vp, vp],
         "dm_server_create": [ctypes.c_int, ctypes.POINTER(CServerConfig), ctypes.POINTER(vp)],
         "dm_server_destroy": [vp],
@@ -235,14 +235,15 @@ class Handle:
         _check(_load().dm_timing_enable(self._h, 1 if enable else 0), "dm_timing_enable")
 
     def timing_read(self, reset: bool = True) -> dict:
-        """{'fwd': (launches, ms, pairs), 'vjp': (...)} from the HIP events the
-        library records around each sweep launch."""
-        a, b, c = CKernelTime(), CKernelTime(), CKernelTime()
-        _check(_load().dm_timing_read(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 1 if reset else 0),
-               "dm_timing_read")
+        """{'fwd': (launches, ms, pairs), 'vjp': ..., 'batch': ..., 'fused': ...}
+        from the HIP events the library records around each sweep launch."""
+        a, b, c, d = CKernelTime(), CKernelTime(), CKernelTime(), CKernelTime()
+        _check(_load().dm_timing_read(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                      1 if reset else 0), "dm_timing_read")
         return {"fwd": (int(a.launches), float(a.ms), float(a.pairs)),
                 "vjp": (int(b.launches), float(b.ms), float(b.pairs)),
-                "batch": (int(c.launches), float(c.ms), float(c.pairs))}
+                "batch": (int(c.launches), float(c.ms), float(c.pairs)),
+                "fused": (int(d.launches), float(d.ms), float(d.pairs))}
 
     def topology(self, faces, n_verts: int | None = None) -> "Topology":
         return Topology(self, faces, n_verts)

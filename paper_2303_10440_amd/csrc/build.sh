@@ -13,7 +13,8 @@ trap 'rm -rf "$TMP"' EXIT
 "$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_precond.hip" -o "$TMP/dm_precond.o"
 "$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_scratch.hip" -o "$TMP/dm_scratch.o"
 "$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_host.cpp" -o "$TMP/dm_host.o"
-"$ROCM/bin/hipcc" -shared --offload-arch=gfx950 -o "$OUT.tmp" "$TMP/dm_kernels.o" "$TMP/dm_precond.o" "$TMP/dm_scratch.o" "$TMP/dm_host.o" \
+"$ROCM/bin/hipcc" "${FLAGS[@]}" -c "$HERE/dm_topo.cpp" -o "$TMP/dm_topo.o"
+"$ROCM/bin/hipcc" -shared --offload-arch=gfx950 -o "$OUT.tmp" "$TMP/dm_kernels.o" "$TMP/dm_precond.o" "$TMP/dm_scratch.o" "$TMP/dm_host.o" "$TMP/dm_topo.o" \
   -L"$ROCM/lib" -lrocfft -Wl,-rpath,"$ROCM/lib"
 mv -f "$OUT.tmp" "$OUT"
 echo "built $OUT"

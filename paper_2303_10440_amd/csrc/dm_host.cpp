@@ -24,6 +24,7 @@
 
 #include "../../include/deltamic.h"
 #include "dm_internal.h"
+#include "dm_topo.h"
 
 using namespace dm;
 
@@ -77,6 +78,23 @@ struct DeviceGuard {
   }
 };
 
+// Limits of a handle's band cache (a band per grid, covariance and threshold:
+// a fit that changes the PSF every step, or a server whose requests carry
+// their own PSFs, would otherwise keep one band per covariance forever).
+// Beyond either limit the least recently used band that no batch in
+// preparation holds is freed.
+constexpr size_t BAND_CACHE_MAX_COUNT = 32;
+constexpr size_t BAND_CACHE_MAX_BYTES = (size_t)4 << 30;
+
+// Second stream of a batch (created on first use, default priority) and the
+// events that fork work onto it and join it back.  A handle has one for
+// dm_batch_run; each serving slot has its own, so batches in flight on
+// different slots do not queue behind each other's second stream.
+struct AuxStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct BandKey {
   int n[3];
   uint32_t spacing[3];
@@ -101,7 +119,7 @@ struct FftPlans {
 // Event pairs recorded around sweep launches while timing is enabled.
 struct TimedLaunch {
   hipEvent_t a = nullptr, b = nullptr;
-  int kind = 0;   // 0 forward sweep, 1 gradient sweep, 2 batched sweep
+  int kind = 0;   // 0 forward sweep, 1 gradient sweep, 2 batched sweep, 3 fused sweep
   double pairs = 0.0;
 };
 
@@ -115,21 +133,19 @@ struct dm_handle {
   size_t ws_bytes = 0;
   std::map<BandKey, BandEntry> bands;
   std::list<BandKey> band_lru;   // front = most recent
+  size_t band_bytes = 0;         // device memory of the cached bands
   BandEntry otf_band;            // band of the last tabulated-OTF call (rebuilt every call)
   std::map<std::tuple<int, int, int>, FftPlans> ffts;
   rocfft_execution_info exec_info = nullptr;
   hipEvent_t last_ev = nullptr;
   bool have_last = false;
-  // Second stream of batched calls (created on first use, default priority)
-  // and the events that fork work onto it and join it back.
-  hipStream_t aux = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  AuxStream aux;   // second stream of dm_batch_run
   int topo_count = 0;
   size_t topo_bytes = 0;
   bool timing = false;
   std::vector<TimedLaunch> pending;   // recorded, not yet read
   std::vector<hipEvent_t> event_pool;
-  dm_kernel_time acc[3] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}, {0, 0.0, 0.0}};
+  dm_kernel_time acc[4] = {{0, 0.0, 0.0}, {0, 0.0, 0.0}, {0, 0.0, 0.0}, {0, 0.0, 0.0}};
 };
 
 // Triangles are kept in strip order: consecutive triangles of a strip share
@@ -148,6 +164,7 @@ struct dm_topology {
   // density weights (dm_topology_set_weights): device [nt] in strip order, or nullptr (all 1)
   float* weights = nullptr;
   int closed_plain = 0;                    // closed and consistently oriented, ignoring weights
+  int lap_mu = 0;                          // bound on the largest eigenvalue of the mesh Laplacian
   std::vector<int32_t> faces_in;           // host copy of the input faces
   std::vector<int32_t> src;                // input face of each strip-order triangle
   size_t bytes = 0;
@@ -182,6 +199,7 @@ bool evict_one_band(dm_handle* h) {
     if (it == h->bands.end() || it->second.pins > 0) continue;
     (void)hipDeviceSynchronize();
     dev_free(h, it->second.mem, it->second.bytes);
+    h->band_bytes -= std::min(h->band_bytes, it->second.bytes);
     h->bands.erase(it);
     h->band_lru.erase(std::next(lit).base());
     return true;
@@ -223,34 +241,13 @@ T* at(dm_handle* h, size_t off) {
 }
 
 dm_status check_grid(const dm_grid* g) {
-  if (!g) return fail(DM_ERR_ARG, "grid is NULL");
-  for (int j = 0; j < 3; ++j) {
-    if (g->n[j] < 1) return fail(DM_ERR_ARG, "grid n[%d] = %d must be >= 1", j, g->n[j]);
-    if (!(g->spacing[j] > 0.0f) || !std::isfinite(g->spacing[j]))
-      return fail(DM_ERR_ARG, "grid spacing[%d] must be finite and > 0", j);
-    if (!std::isfinite(g->origin[j])) return fail(DM_ERR_ARG, "grid origin[%d] must be finite", j);
-  }
-  const int64_t npos = (int64_t)g->n[0] * g->n[1] * (g->n[2] / 2 + 1);
-  if (npos > (int64_t)1 << 29) return fail(DM_ERR_ARG, "grid too large (%lld half-spectrum positions)", (long long)npos);
-  if (!(g->band_tau >= 0.0f) || std::isnan(g->band_tau)) return fail(DM_ERR_ARG, "band_tau must be >= 0");
-  if (g->mode != DM_VOLUME && g->mode != DM_SURFACE) return fail(DM_ERR_ARG, "unknown mode %d", g->mode);
-  return DM_OK;
+  const Check c = validate_grid(g);
+  return c.st == DM_OK ? DM_OK : fail(c.st, "%s", c.msg.c_str());
 }
 
 dm_status check_psf(const dm_psf* p) {
-  if (!p) return fail(DM_ERR_ARG, "psf is NULL");
-  for (int j = 0; j < 6; ++j)
-    if (!std::isfinite(p->sigma[j])) return fail(DM_ERR_PSF, "sigma[%d] is not finite", j);
-  // Cholesky of [[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]] in double.
-  const double a = p->sigma[0], b = p->sigma[3], c = p->sigma[4], d = p->sigma[1], e = p->sigma[5], f = p->sigma[2];
-  if (!(a > 0)) return fail(DM_ERR_PSF, "covariance not positive definite (xx <= 0)");
-  const double l21 = b / std::sqrt(a), l31 = c / std::sqrt(a);
-  const double d2 = d - l21 * l21;
-  if (!(d2 > 0)) return fail(DM_ERR_PSF, "covariance not positive definite");
-  const double l32 = (e - l31 * l21) / std::sqrt(d2);
-  const double d3 = f - l31 * l31 - l32 * l32;
-  if (!(d3 > 0)) return fail(DM_ERR_PSF, "covariance not positive definite");
-  return DM_OK;
+  const Check c = validate_psf(p);
+  return c.st == DM_OK ? DM_OK : fail(c.st, "%s", c.msg.c_str());
 }
 
 GridC make_gridc(const dm_grid* g) {
@@ -318,12 +315,15 @@ dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t 
   int64_t total = 0;
   HIP_TRY(hipMemcpyAsync(&total, at<int64_t>(h, o_tot), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // allocate the band (evicting older bands if the budget requires)
+  // allocate the band (evicting the least recently used unpinned bands if the
+  // budget or the cache's own limits require)
   Carver bc;
   const int64_t ne = std::max<int64_t>(total, 1);
   const size_t o_kf = bc.take<float4>(ne), o_w = bc.take<float>(ne), o_pos = bc.take<int32_t>(ne),
                o_map = bc.take<int32_t>(n_pos);
-  while (h->budget && h->in_use + bc.off > h->budget && evict_one_band(h)) {
+  while (((h->budget && h->in_use + bc.off > h->budget) || h->bands.size() >= BAND_CACHE_MAX_COUNT ||
+          h->band_bytes + bc.off > BAND_CACHE_MAX_BYTES) &&
+         evict_one_band(h)) {
   }
   BandEntry be;
   DM_TRY(dev_alloc(h, &be.mem, bc.off));
@@ -343,6 +343,7 @@ dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t 
   }
   be.pins = pin ? 1 : 0;
   h->bands[key] = be;
+  h->band_bytes += be.bytes;
   h->band_lru.push_front(key);
   *out = be.dev;
   return DM_OK;
@@ -440,88 +441,6 @@ dm_status check_mesh(const dm_mesh* m, int mode) {
   return DM_OK;
 }
 
-// Greedy triangle strips.  From each unused seed triangle (in input order)
-// the strip is grown across the edge formed by its last two vertices while the
-// triangle across it is unused; of the seed's three rotations the longest
-// strip is kept.  Output: faces in strip order (s_i, s_i+1, s_i+2) and flags
-// (strip start; odd permutation of the input face, i.e. reversed orientation).
-int build_strips(const std::vector<int32_t>& F, std::vector<int32_t>& Fs, std::vector<int32_t>& flags,
-                 std::vector<int32_t>* src = nullptr) {
-  const int nt = (int)(F.size() / 3);
-  std::vector<std::pair<uint64_t, int>> edges;
-  edges.reserve(F.size());
-  for (int t = 0; t < nt; ++t)
-    for (int p = 0; p < 3; ++p) {
-      const uint32_t a = (uint32_t)F[3 * t + p], b = (uint32_t)F[3 * t + (p + 1) % 3];
-      edges.push_back({((uint64_t)std::min(a, b) << 32) | std::max(a, b), t});
-    }
-  std::sort(edges.begin(), edges.end());
-  std::vector<char> used((size_t)nt, 0), trial((size_t)nt, 0);
-  // the unused triangle other than `from` across edge {x, y}, or -1
-  auto across = [&](int32_t x, int32_t y, const std::vector<char>& taken) {
-    const uint64_t key = ((uint64_t)std::min((uint32_t)x, (uint32_t)y) << 32) | std::max((uint32_t)x, (uint32_t)y);
-    auto it = std::lower_bound(edges.begin(), edges.end(), std::make_pair(key, -1));
-    for (; it != edges.end() && it->first == key; ++it)
-      if (!used[(size_t)it->second] && !taken[(size_t)it->second]) return it->second;
-    return -1;
-  };
-  auto third = [&](int u, int32_t x, int32_t y) {
-    for (int p = 0; p < 3; ++p) {
-      const int32_t z = F[3 * u + p];
-      if (z != x && z != y) return z;
-    }
-    return F[3 * u];
-  };
-  Fs.clear();
-  flags.clear();
-  Fs.reserve(F.size());
-  flags.reserve((size_t)nt);
-  if (src) {
-    src->clear();
-    src->reserve((size_t)nt);
-  }
-  int n_strips = 0;
-  std::vector<int> tris, best_tris;
-  std::vector<int32_t> seq, best_seq;
-  for (int s = 0; s < nt; ++s) {
-    if (used[(size_t)s]) continue;
-    best_tris.clear();
-    for (int r = 0; r < 3; ++r) {
-      seq = {F[3 * s + r], F[3 * s + (r + 1) % 3], F[3 * s + (r + 2) % 3]};
-      tris = {s};
-      trial[(size_t)s] = 1;
-      for (;;) {
-        const int32_t x = seq[seq.size() - 2], y = seq.back();
-        const int u = across(x, y, trial);
-        if (u < 0) break;
-        trial[(size_t)u] = 1;
-        tris.push_back(u);
-        seq.push_back(third(u, x, y));
-      }
-      for (int u : tris) trial[(size_t)u] = 0;
-      if (tris.size() > best_tris.size()) {
-        best_tris = tris;
-        best_seq = seq;
-      }
-    }
-    for (size_t i = 0; i < best_tris.size(); ++i) {
-      const int u = best_tris[i];
-      used[(size_t)u] = 1;
-      const int32_t a = best_seq[i], b = best_seq[i + 1], c = best_seq[i + 2];
-      Fs.push_back(a);
-      Fs.push_back(b);
-      Fs.push_back(c);
-      // (a, b, c) is a rotation of the input face (same orientation) or not
-      bool same = false;
-      for (int r = 0; r < 3; ++r)
-        same = same || (F[3 * u + r] == a && F[3 * u + (r + 1) % 3] == b && F[3 * u + (r + 2) % 3] == c);
-      flags.push_back((i == 0 ? TRI_STRIP_START : 0) | (same ? 0 : TRI_REVERSED));
-      if (src) src->push_back(u);
-    }
-    ++n_strips;
-  }
-  return n_strips;
-}
 
 // Launch geometry of the two sweeps.
 struct SweepPlan {
@@ -567,6 +486,50 @@ SweepPlan plan_vjp(int64_t nE, int nt, int mode) {
   return sp;
 }
 
+// Fused sweep (forward and gradient in one pass): one entry chunk of
+// fused_chunk(mode) entries per block times triangle ranges of tpb, about
+// FUSED_TARGET_BLOCKS blocks in all (ranges of at least 32 triangles).  The
+// forward partials take 8 B x entries per triangle range and the gradient
+// partials 4 B x channels x triangles per entry chunk.  In the returned plan
+// n_chunks/per_chunk/tpb describe the entry chunks (gradient partials); the
+// triangle ranges are fused_fwd_plan's.
+constexpr int64_t FUSED_TARGET_BLOCKS = 20480;
+
+SweepPlan plan_fused(int64_t nE, int nt, int mode) {
+  SweepPlan sp;
+  const int64_t chunk = fused_chunk(mode);
+  const int64_t units = std::max<int64_t>(1, (nE + chunk - 1) / chunk);
+  sp.sub = 1;
+  sp.n_chunks = (int)units;
+  sp.per_chunk = (int)chunk;
+  const int64_t want = (FUSED_TARGET_BLOCKS + units - 1) / units;
+  const int64_t most = std::max<int64_t>(1, nt / 32);
+  const int64_t tchunks = std::max<int64_t>(1, std::min(want, most));
+  sp.tpb = (int)std::max<int64_t>(1, (nt + tchunks - 1) / tchunks);
+  return sp;
+}
+
+// The fused plan of a request inside a batch's shared launch: the same entry
+// chunks, triangle ranges of at least FUSED_BATCH_TILE_PAIRS / fused_chunk
+// triangles (the whole mesh when it is smaller), so that many small requests
+// do not turn into many small tiles; the shared queue fills the GPU.
+constexpr int64_t FUSED_BATCH_TILE_PAIRS = (int64_t)1 << 22;
+
+SweepPlan plan_fused_batch(int64_t nE, int nt, int mode) {
+  SweepPlan sp = plan_fused(nE, nt, mode);
+  const int64_t want = (FUSED_BATCH_TILE_PAIRS + fused_chunk(mode) - 1) / fused_chunk(mode);
+  sp.tpb = (int)std::max<int64_t>(sp.tpb, std::min<int64_t>(std::max(nt, 1), want));
+  return sp;
+}
+
+// Triangle ranges of a fused plan as a forward plan (the forward partials).
+SweepPlan fused_fwd_plan(const SweepPlan& v, int nt) {
+  SweepPlan sp;
+  sp.per_chunk = v.tpb;
+  sp.n_chunks = std::max(1, (nt + v.tpb - 1) / v.tpb);
+  return sp;
+}
+
 hipEvent_t pooled_event(dm_handle* h) {
   if (!h->event_pool.empty()) {
     hipEvent_t e = h->event_pool.back();
@@ -604,11 +567,18 @@ dm_status begin_call(dm_handle* h, hipStream_t s) {
   return DM_OK;
 }
 
-dm_status ensure_aux(dm_handle* h) {
-  if (!h->aux) HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-  if (!h->fork_ev) HIP_TRY(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
-  if (!h->join_ev) HIP_TRY(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
+dm_status ensure_aux(AuxStream* a) {
+  if (!a->s) HIP_TRY(hipStreamCreateWithFlags(&a->s, hipStreamNonBlocking));
+  if (!a->fork) HIP_TRY(hipEventCreateWithFlags(&a->fork, hipEventDisableTiming));
+  if (!a->join) HIP_TRY(hipEventCreateWithFlags(&a->join, hipEventDisableTiming));
   return DM_OK;
+}
+
+void destroy_aux(AuxStream* a) {
+  if (a->fork) (void)hipEventDestroy(a->fork);
+  if (a->join) (void)hipEventDestroy(a->join);
+  if (a->s) (void)hipStreamDestroy(a->s);
+  *a = AuxStream{};
 }
 
 dm_status end_call(dm_handle* h, hipStream_t s) {
@@ -616,6 +586,30 @@ dm_status end_call(dm_handle* h, hipStream_t s) {
   h->have_last = true;
   return DM_OK;
 }
+
+// A call's ordering on the handle: begin() makes s wait for the handle's
+// previous call, end() records the handle's last-call event on s.  If the
+// call fails after begin() (work may already be enqueued on s), the
+// destructor still records the event, so that the next call on any stream
+// waits for what this one left running in the shared workspace.
+struct CallScope {
+  dm_handle* h;
+  hipStream_t s;
+  bool open = false;
+  CallScope(dm_handle* h_, hipStream_t s_) : h(h_), s(s_) {}
+  dm_status begin() {
+    DM_TRY(begin_call(h, s));
+    open = true;
+    return DM_OK;
+  }
+  dm_status end() {
+    open = false;
+    return end_call(h, s);
+  }
+  ~CallScope() {
+    if (open && hipEventRecord(h->last_ev, s) == hipSuccess) h->have_last = true;
+  }
+};
 
 dm_status zero_fill(float* p, int64_t n, hipStream_t s) {
   if (!p || n <= 0) return DM_OK;
@@ -640,6 +634,7 @@ struct ReqPlan {
   int mode = 0, nt = 0, nv = 0, nc = 3, prep_blocks = 1, adj_blocks = 1;
   int64_t nvox = 0, nE = 0;
   bool want_vjp = false, need_spec = false, empty = false, pinned = false;
+  bool fused = false;    // forward and gradient sweeps in one launch (k_fused_lanes)
   bool direct = false;   // in a batch: large enough to run its own sweep launches
   GridC gc{};
   BandDev b{};
@@ -655,16 +650,19 @@ struct ReqPlan {
 };
 
 // Batch chunking depends on the request alone, so a request's result is the
-// same whichever other requests share its batch.
-// At least 640 triangles per forward tile so small requests still give long
-// sweeps, at most 8 forward chunks so the partials of large requests stay
-// bounded (8 B x entries x 8).  Gradient items cover sub x vjp_chunk(mode) entries
-// (at most 256 chunks, as in plan_vjp) and up to VJP_TPB_MAX triangles.
-// A request of at least this many (entry, triangle) pairs fills the GPU with
-// its own sweep launches (about 1 ms each), so inside a batch it runs them
-// (the single-call plans) instead of joining the shared persistent launch.
-// The choice depends on the request alone, so its result is still the same
-// in any batch.
+// same whichever other requests share its batch.  A request that wants the
+// image (or dL/dSigma) and the vertex gradient runs the tiles of its
+// single-call fused plan, so its outputs are bitwise those of dm_render_vjp.
+// Forward-only and gradient-only requests: at least 640 triangles per forward
+// tile so small requests still give long sweeps, at most 8 forward chunks so
+// the partials of large requests stay bounded (8 B x entries x 8); gradient
+// items cover sub x vjp_chunk(mode) entries (at most 256 chunks, as in
+// plan_vjp) and up to VJP_TPB_MAX triangles.
+// The server runs a request of at least this many (entry, triangle) pairs with
+// its own sweep launches (it fills the GPU alone), after the shared launch of
+// the batch's smaller requests, so that those complete first; dm_batch_run
+// puts every request in the shared launch.  The choice depends on the request
+// alone, so its result is still the same in any batch.
 constexpr double BATCH_DIRECT_PAIRS = 5e8;
 
 SweepPlan plan_fwd_batch(int64_t nE, int nt) {
@@ -683,7 +681,10 @@ SweepPlan plan_vjp_batch(int64_t nE, int nt, int mode) {
   return sp;
 }
 
-dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch) {
+// batch: the request is part of a batch; requests of at least direct_pairs
+// (entry, triangle) pairs then run their own sweep launches instead of joining
+// the shared persistent launch.
+dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch, double direct_pairs = INFINITY) {
   P.mode = P.g.mode;
   P.gc = make_gridc(&P.g);
   P.nt = P.m->topo->nt;
@@ -701,10 +702,18 @@ dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch) {
   if (P.image || P.want_vjp) DM_TRY(get_fft(h, &P.g, &P.fp));
   P.empty = P.nE == 0 || P.nt == 0;
   P.need_spec = (P.image && !P.spec_in) || (P.dS && !P.spec_in) || P.spec_out;
-  P.direct = batch && (double)P.nE * P.nt >= BATCH_DIRECT_PAIRS;
+  P.direct = batch && (double)P.nE * P.nt >= direct_pairs;
   const bool shared = batch && !P.direct;
-  P.fsp = shared ? plan_fwd_batch(P.nE, P.nt) : plan_fwd(P.nE, P.nt);
-  P.vsp = shared ? plan_vjp_batch(P.nE, P.nt, P.g.mode) : plan_vjp(P.nE, P.nt, P.g.mode);
+  // the forward value comes with the gradient sweep when both are wanted (in a
+  // batch too: the shared launch runs the single-call fused plan's tiles)
+  P.fused = P.need_spec && P.want_vjp && P.dV;
+  if (P.fused) {
+    P.vsp = shared ? plan_fused_batch(P.nE, P.nt, P.g.mode) : plan_fused(P.nE, P.nt, P.g.mode);
+    P.fsp = fused_fwd_plan(P.vsp, P.nt);
+  } else {
+    P.fsp = shared ? plan_fwd_batch(P.nE, P.nt) : plan_fwd(P.nE, P.nt);
+    P.vsp = shared ? plan_vjp_batch(P.nE, P.nt, P.g.mode) : plan_vjp(P.nE, P.nt, P.g.mode);
+  }
   P.nc = nchannels(P.mode);
   P.prep_blocks = mesh_prep_blocks(P.nt);
   P.adj_blocks = adjoint_blocks(P.gc);
@@ -759,9 +768,16 @@ dm_status stage_pre(dm_handle* h, ReqPlan& P, hipStream_t s) {
   return DM_OK;
 }
 
-// The two sweeps as separate launches (single-request path).
+// The two sweeps as separate launches, or the fused sweep (single-request path).
 dm_status stage_sweeps(dm_handle* h, ReqPlan& P, hipStream_t s) {
   if (P.empty) return DM_OK;
+  if (P.fused) {
+    SweepTimer tm(h, s, 3, (double)P.nE * P.nt);
+    HIP_TRY(launch_fused_lanes(P.mode, P.gc, P.ptr<float>(P.o_rec), P.nt, P.vsp.tpb, P.ptr<float4>(P.o_erec), P.nE,
+                               P.ptr<float>(P.o_vpart), P.ptr<float2>(P.o_part), s));
+    tm.done();
+    return DM_OK;
+  }
   if (P.need_spec) {
     SweepTimer tm(h, s, 0, (double)P.nE * P.nt);
     HIP_TRY(launch_fwd_lanes(P.mode, P.b.kf, P.nE, P.ptr<float>(P.o_rec), P.nt, P.fsp.per_chunk, P.fsp.n_chunks,
@@ -779,7 +795,7 @@ dm_status stage_sweeps(dm_handle* h, ReqPlan& P, hipStream_t s) {
 
 // Work items of this request for the persistent batched sweep.
 void add_items(const ReqPlan& P, int req, std::vector<SweepItem>& items, std::vector<double>& cost) {
-  if (P.empty || P.direct) return;
+  if (P.empty || P.direct || P.fused) return;   // fused tiles are implicit (layout_batch)
   if (P.need_spec)
     for (int c = 0; c < P.fsp.n_chunks; ++c) {
       const int tris = std::min(P.nt, (c + 1) * P.fsp.per_chunk) - c * P.fsp.per_chunk;
@@ -810,6 +826,8 @@ SweepReq sweep_req(const ReqPlan& P) {
   q.tpx = P.gc.two_pi_over_L[0];
   q.tpy = P.gc.two_pi_over_L[1];
   q.tpz = P.gc.two_pi_over_L[2];
+  q.tile0 = 0;
+  q.ntr = P.fsp.n_chunks;
   q.kf = P.b.kf;
   q.rec = P.empty ? nullptr : P.ptr<float>(P.o_rec);
   q.fpart = P.need_spec && !P.empty ? P.ptr<float2>(P.o_part) : nullptr;
@@ -850,7 +868,8 @@ dm_status stage_post(dm_handle* h, ReqPlan& P, hipStream_t s) {
 dm_status render_impl(dm_handle* h, const dm_mesh* m, const dm_psf* psf, const dm_grid* g, float* image,
                       float* spec_out, const float* dLdI, float* dV, float* dS, const float* spec_in, hipStream_t s,
                       const float2* otf = nullptr) {
-  DM_TRY(begin_call(h, s));
+  CallScope call(h, s);
+  DM_TRY(call.begin());
   ReqPlan P;
   P.m = m;
   P.g = *g;
@@ -868,7 +887,7 @@ dm_status render_impl(dm_handle* h, const dm_mesh* m, const dm_psf* psf, const d
   DM_TRY(stage_pre(h, P, s));
   DM_TRY(stage_sweeps(h, P, s));
   DM_TRY(stage_post(h, P, s));
-  return end_call(h, s);
+  return call.end();
 }
 
 dm_status check_request(const dm_request& r, int i) {
@@ -897,7 +916,14 @@ struct BatchLayout {
   std::vector<size_t> off;
   std::vector<SweepItem> items;   // grouped by (kind, mode), each group longest first
   std::vector<SweepReq> reqs;
-  int group_end[4] = {0, 0, 0, 0};
+  int group_end[BATCH_GROUPS] = {};
+  // fused requests of the shared launch per density, in queue order (largest
+  // tiles first), with their first tiles; the descriptors are filled in when
+  // the batch's memory is known
+  std::vector<int> fused_order[2], fused_tile0[2];
+  int fused_tiles[2] = {0, 0};
+  std::vector<SweepReq> fused_reqs[2];
+  size_t o_fused[2] = {0, 0};
   size_t o_items = 0, o_reqs = 0, o_counter = 0, total = 0;
   double pairs = 0.0;
 };
@@ -923,14 +949,32 @@ void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
     return cost[a] > cost[b];
   });
   L.items.resize(items.size());
-  int count[4] = {0, 0, 0, 0};
+  int count[BATCH_GROUPS] = {};
   for (size_t i = 0; i < order.size(); ++i) {
     L.items[i] = items[order[i]];
     count[group(order[i])]++;
   }
-  for (int g = 0, acc = 0; g < 4; ++g) {
+  for (int g = 0, acc = 0; g < BATCH_GROUPS; ++g) {
     acc += count[g];
     L.group_end[g] = acc;
+  }
+  for (int m = 0; m < 2; ++m) {
+    std::vector<int>& ord = L.fused_order[m];
+    ord.clear();
+    L.fused_tile0[m].clear();
+    for (size_t i = 0; i < n; ++i)
+      if (P[i].fused && !P[i].direct && !P[i].empty && P[i].mode == m) ord.push_back((int)i);
+    // largest tiles first (longest-processing-time order), then request order
+    auto tile_pairs = [&](int i) { return (double)P[(size_t)i].vsp.per_chunk * P[(size_t)i].vsp.tpb; };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return tile_pairs(a) > tile_pairs(b); });
+    int acc = 0;
+    for (int i : ord) {
+      L.fused_tile0[m].push_back(acc);
+      acc += P[(size_t)i].vsp.n_chunks * P[(size_t)i].fsp.n_chunks;
+    }
+    L.fused_tiles[m] = acc;
+    L.o_fused[m] = L.total;
+    L.total += align_up(std::max<size_t>(1, ord.size()) * sizeof(SweepReq));
   }
   L.o_items = L.total;
   L.total += align_up(std::max<size_t>(1, L.items.size()) * sizeof(SweepItem));
@@ -947,13 +991,23 @@ template <typename Done>
 dm_status enqueue_batch_rest(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s,
                              hipStream_t s2, Done& done) {
   const size_t n = P.size();
-  if (!L.items.empty()) {
-    HIP_TRY(hipMemcpyAsync(base + L.o_items, L.items.data(), L.items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
-                           s));
+  if (!L.items.empty() || L.fused_tiles[0] > 0 || L.fused_tiles[1] > 0) {
+    if (!L.items.empty())
+      HIP_TRY(hipMemcpyAsync(base + L.o_items, L.items.data(), L.items.size() * sizeof(SweepItem),
+                             hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(base + L.o_reqs, L.reqs.data(), n * sizeof(SweepReq), hipMemcpyHostToDevice, s));
+    const SweepReq* freqs[2];
+    int n_freqs[2];
+    for (int m = 0; m < 2; ++m) {
+      freqs[m] = reinterpret_cast<const SweepReq*>(base + L.o_fused[m]);
+      n_freqs[m] = (int)L.fused_reqs[m].size();
+      if (n_freqs[m] > 0)
+        HIP_TRY(hipMemcpyAsync(base + L.o_fused[m], L.fused_reqs[m].data(), L.fused_reqs[m].size() * sizeof(SweepReq),
+                               hipMemcpyHostToDevice, s));
+    }
     SweepTimer tm(h, s, 2, L.pairs);
     HIP_TRY(launch_batch_sweep(reinterpret_cast<const SweepItem*>(base + L.o_items), L.group_end,
-                               reinterpret_cast<const SweepReq*>(base + L.o_reqs),
+                               reinterpret_cast<const SweepReq*>(base + L.o_reqs), freqs, n_freqs, L.fused_tiles,
                                reinterpret_cast<int*>(base + L.o_counter), s));
     tm.done();
   }
@@ -976,15 +1030,15 @@ dm_status enqueue_batch_rest(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout&
 // Enqueues a planned batch on s: every request's pre-steps, the shared
 // persistent launch and the post-steps of the requests in it, then each large
 // request's own sweeps and post-steps.  Large requests alternate between s
-// and the handle's second stream (forked after the pre-steps, joined back
-// into s at the end), so one request's post-steps and the tail of its sweeps
+// and the second stream aux (forked after the pre-steps, joined back into s
+// at the end), so one request's post-steps and the tail of its sweeps
 // overlap the next one's sweeps; each request works in its own region of the
 // batch memory, and its FFTs get its own work buffer.  With req_done, an
 // event is recorded after each request's last step (req_done[i] for request
 // i, on the stream that ran it), so that a caller can hand out results as
 // they complete.
 dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s,
-                        const std::vector<hipEvent_t>* req_done = nullptr) {
+                        AuxStream* aux, const std::vector<hipEvent_t>* req_done = nullptr) {
   const size_t n = P.size();
   L.reqs.resize(n);
   int n_direct = 0;
@@ -993,6 +1047,14 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
     L.reqs[i] = sweep_req(P[i]);
     if (P[i].direct && !P[i].empty) ++n_direct;
   }
+  for (int m = 0; m < 2; ++m) {
+    L.fused_reqs[m].clear();
+    for (size_t k = 0; k < L.fused_order[m].size(); ++k) {
+      SweepReq q = L.reqs[(size_t)L.fused_order[m][k]];
+      q.tile0 = L.fused_tile0[m][k];
+      L.fused_reqs[m].push_back(q);
+    }
+  }
   auto done = [&](size_t i, hipStream_t st) -> dm_status {
     if (req_done && (*req_done)[i]) HIP_TRY(hipEventRecord((*req_done)[i], st));
     return DM_OK;
@@ -1000,16 +1062,16 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
   for (size_t i = 0; i < n; ++i) DM_TRY(stage_pre(h, P[i], s));
   hipStream_t s2 = s;
   if (n_direct >= 2) {
-    DM_TRY(ensure_aux(h));
-    HIP_TRY(hipEventRecord(h->fork_ev, s));
-    HIP_TRY(hipStreamWaitEvent(h->aux, h->fork_ev, 0));
-    s2 = h->aux;
+    DM_TRY(ensure_aux(aux));
+    HIP_TRY(hipEventRecord(aux->fork, s));
+    HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
+    s2 = aux->s;
   }
   const dm_status st = enqueue_batch_rest(h, P, L, base, s, s2, done);
   if (s2 != s) {
     // join even after a failed enqueue, so that s never runs ahead of s2
-    HIP_TRY(hipEventRecord(h->join_ev, s2));
-    HIP_TRY(hipStreamWaitEvent(s, h->join_ev, 0));
+    HIP_TRY(hipEventRecord(aux->join, s2));
+    HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
   }
   return st;
 }
@@ -1064,9 +1126,7 @@ dm_status dm_destroy(dm_handle* h) {
   for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
   if (h->ws) (void)hipFree(h->ws);
   if (h->last_ev) (void)hipEventDestroy(h->last_ev);
-  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
-  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
-  if (h->aux) (void)hipStreamDestroy(h->aux);
+  destroy_aux(&h->aux);
   delete h;
   return DM_OK;
 }
@@ -1079,7 +1139,7 @@ dm_status dm_timing_enable(dm_handle* h, int enable) {
 }
 
 dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time* vjp_sweep,
-                         dm_kernel_time* batch_sweep, int reset) {
+                         dm_kernel_time* batch_sweep, dm_kernel_time* fused_sweep, int reset) {
   g_err.clear();
   if (!h) return fail(DM_ERR_ARG, "NULL handle");
   DeviceGuard dg(h->device);
@@ -1097,7 +1157,8 @@ dm_status dm_timing_read(dm_handle* h, dm_kernel_time* fwd_sweep, dm_kernel_time
   if (fwd_sweep) *fwd_sweep = h->acc[0];
   if (vjp_sweep) *vjp_sweep = h->acc[1];
   if (batch_sweep) *batch_sweep = h->acc[2];
-  if (reset) h->acc[0] = h->acc[1] = h->acc[2] = dm_kernel_time{0, 0.0, 0.0};
+  if (fused_sweep) *fused_sweep = h->acc[3];
+  if (reset) h->acc[0] = h->acc[1] = h->acc[2] = h->acc[3] = dm_kernel_time{0, 0.0, 0.0};
   return DM_OK;
 }
 
@@ -1123,95 +1184,45 @@ dm_status dm_topology_create(dm_handle* h, const int32_t* faces, int32_t n_faces
     else
       memcpy(F.data(), faces, F.size() * 4);
   }
-  for (size_t i = 0; i < F.size(); ++i)
-    if (F[i] < 0 || F[i] >= n_verts)
-      return fail(DM_ERR_MESH, "face %zu references vertex %d outside [0, %d)", i / 3, F[i], n_verts);
-  // closed and consistently oriented: each directed edge once, with its reverse present
-  std::vector<uint64_t> e;
-  e.reserve(F.size());
-  for (int t = 0; t < n_faces; ++t)
-    for (int p = 0; p < 3; ++p) {
-      const uint32_t a = (uint32_t)F[3 * t + p], b = (uint32_t)F[3 * t + (p + 1) % 3];
-      e.push_back(((uint64_t)a << 32) | b);
-    }
-  std::sort(e.begin(), e.end());
-  bool closed = n_faces > 0 && std::adjacent_find(e.begin(), e.end()) == e.end();
-  if (closed)
-    for (uint64_t x : e) {
-      const uint64_t r = (x << 32) | (x >> 32);
-      if (!std::binary_search(e.begin(), e.end(), r)) {
-        closed = false;
-        break;
-      }
-    }
-  std::vector<int32_t> Fs, fl, src;
-  const int n_strips = build_strips(F, Fs, fl, &src);
-  std::vector<int32_t> faces_in = F;
-  F.swap(Fs);
-  // vertex incidence (CSR)
-  std::vector<int32_t> off((size_t)n_verts + 1, 0), ent(F.size());
-  for (size_t i = 0; i < F.size(); ++i) off[(size_t)F[i] + 1]++;
-  for (int v = 0; v < n_verts; ++v) off[v + 1] += off[v];
-  std::vector<int32_t> fill(off.begin(), off.end() - 1);
-  for (size_t i = 0; i < F.size(); ++i) ent[fill[F[i]]++] = (int32_t)i;   // i = 3 t + p
-  // vertex adjacency: both directions of every undirected mesh edge, unique
-  std::vector<uint64_t> und;
-  und.reserve(2 * e.size());
-  for (uint64_t x : e) {
-    const uint64_t a = x >> 32, b = x & 0xffffffffu;
-    if (a == b) continue;
-    und.push_back((a << 32) | b);
-    und.push_back((b << 32) | a);
-  }
-  std::sort(und.begin(), und.end());
-  und.erase(std::unique(und.begin(), und.end()), und.end());
-  std::vector<int32_t> aoff((size_t)n_verts + 1, 0), anbr(und.size());
-  for (size_t i = 0; i < und.size(); ++i) {
-    aoff[(size_t)(und[i] >> 32) + 1]++;
-    anbr[i] = (int32_t)(und[i] & 0xffffffffu);
-  }
-  for (int v = 0; v < n_verts; ++v) aoff[v + 1] += aoff[v];
-  int max_deg = 0;
-  for (int v = 0; v < n_verts; ++v) max_deg = std::max(max_deg, aoff[v + 1] - aoff[v]);
-  std::vector<int32_t> atab;
-  if (max_deg <= LAP_TABLE_W) {
-    atab.assign((size_t)n_verts * LAP_TABLE_W, -1);
-    for (int v = 0; v < n_verts; ++v)
-      for (int o = aoff[v]; o < aoff[v + 1]; ++o) atab[(size_t)v * LAP_TABLE_W + (o - aoff[v])] = anbr[o];
-  }
+  TopoTables T;
+  const Check c = build_topology(F, n_verts, &T);
+  if (c.st != DM_OK) return fail(c.st, "%s", c.msg.c_str());
   auto t = std::make_unique<dm_topology>();
   t->h = h;
   t->nt = n_faces;
   t->nv = n_verts;
-  t->closed = closed ? 1 : 0;
+  t->closed = T.closed ? 1 : 0;
   t->closed_plain = t->closed;
-  t->n_strips = n_strips;
-  t->faces_in.swap(faces_in);
-  t->src.swap(src);
-  const size_t bf = align_up(F.size() * 4), bo = align_up(off.size() * 4), be = align_up(ent.size() * 4),
-               bl = align_up(fl.size() * 4), bao = align_up(aoff.size() * 4), ban = align_up(anbr.size() * 4),
-               bat = align_up(atab.size() * 4);
+  t->n_strips = T.n_strips;
+  t->lap_mu = T.lap_mu;
+  t->faces_in.swap(F);
+  t->src.swap(T.src);
+  const std::vector<int32_t>& Fs = T.faces;
+  const size_t bf = align_up(Fs.size() * 4), bo = align_up(T.csr_off.size() * 4), be = align_up(T.csr_ent.size() * 4),
+               bl = align_up(T.flags.size() * 4), bao = align_up(T.adj_off.size() * 4),
+               ban = align_up(T.adj_nbr.size() * 4), bat = align_up(T.adj_tab.size() * 4);
   void* mem = nullptr;
   DM_TRY(dev_alloc(h, &mem, bf + bo + be + bl + bao + ban + bat));
   t->bytes = bf + bo + be + bl + bao + ban + bat;
-  t->faces = static_cast<int32_t*>(mem);
-  t->csr_off = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf);
-  t->csr_ent = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo);
-  t->flags = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be);
-  t->adj_off = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl);
-  t->adj_nbr = reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl + bao);
-  t->adj_tab = atab.empty() ? nullptr
-                            : reinterpret_cast<int32_t*>(static_cast<char*>(mem) + bf + bo + be + bl + bao + ban);
+  char* base = static_cast<char*>(mem);
+  t->faces = reinterpret_cast<int32_t*>(base);
+  t->csr_off = reinterpret_cast<int32_t*>(base + bf);
+  t->csr_ent = reinterpret_cast<int32_t*>(base + bf + bo);
+  t->flags = reinterpret_cast<int32_t*>(base + bf + bo + be);
+  t->adj_off = reinterpret_cast<int32_t*>(base + bf + bo + be + bl);
+  t->adj_nbr = reinterpret_cast<int32_t*>(base + bf + bo + be + bl + bao);
+  t->adj_tab = T.adj_tab.empty() ? nullptr : reinterpret_cast<int32_t*>(base + bf + bo + be + bl + bao + ban);
   hipError_t err = hipSuccess;
-  if (!F.empty()) err = hipMemcpy(t->faces, F.data(), F.size() * 4, hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(t->csr_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
-  if (err == hipSuccess && !ent.empty()) err = hipMemcpy(t->csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice);
-  if (err == hipSuccess && !fl.empty()) err = hipMemcpy(t->flags, fl.data(), fl.size() * 4, hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(t->adj_off, aoff.data(), aoff.size() * 4, hipMemcpyHostToDevice);
-  if (err == hipSuccess && !anbr.empty())
-    err = hipMemcpy(t->adj_nbr, anbr.data(), anbr.size() * 4, hipMemcpyHostToDevice);
-  if (err == hipSuccess && !atab.empty())
-    err = hipMemcpy(t->adj_tab, atab.data(), atab.size() * 4, hipMemcpyHostToDevice);
+  auto up = [&](int32_t* dst, const std::vector<int32_t>& v) {
+    if (err == hipSuccess && !v.empty()) err = hipMemcpy(dst, v.data(), v.size() * 4, hipMemcpyHostToDevice);
+  };
+  up(t->faces, Fs);
+  up(t->csr_off, T.csr_off);
+  up(t->csr_ent, T.csr_ent);
+  up(t->flags, T.flags);
+  up(t->adj_off, T.adj_off);
+  up(t->adj_nbr, T.adj_nbr);
+  if (t->adj_tab) up(t->adj_tab, T.adj_tab);
   if (err != hipSuccess) {
     dev_free(h, mem, t->bytes);
     return fail(DM_ERR_DEVICE, "topology upload: %s", hipGetErrorString(err));
@@ -1268,8 +1279,8 @@ dm_status dm_laplace_smooth(dm_handle* h, dm_topology* t, float lambda, const fl
     t->smooth_ws = static_cast<float*>(mem);
     t->smooth_bytes = need;
   }
-  HIP_TRY(launch_laplace_smooth(t->nv, t->adj_off, t->adj_nbr, t->adj_tab, lambda, grad, out, t->smooth_ws, max_iter,
-                                tol, info, static_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_laplace_smooth(t->nv, t->adj_off, t->adj_nbr, t->adj_tab, t->lap_mu, lambda, grad, out,
+                                t->smooth_ws, max_iter, tol, info, static_cast<hipStream_t>(stream)));
   return DM_OK;
 }
 
@@ -1284,31 +1295,9 @@ dm_status dm_topology_set_weights(dm_topology* t, const float* weights) {
     t->closed = t->closed_plain;
     return DM_OK;
   }
-  for (int i = 0; i < t->nt; ++i)
-    if (!std::isfinite(weights[i])) return fail(DM_ERR_ARG, "weight of face %d is not finite", i);
-  // weighted closure: across every edge the weights of the incident faces,
-  // signed by the direction in which each face runs along the edge, cancel
-  std::vector<std::pair<uint64_t, std::pair<double, double>>> e;   // edge -> (signed sum, sum of |w|)
-  e.reserve((size_t)t->nt * 3);
-  for (int f = 0; f < t->nt; ++f)
-    for (int p = 0; p < 3; ++p) {
-      const uint32_t a = (uint32_t)t->faces_in[3 * f + p], b = (uint32_t)t->faces_in[3 * f + (p + 1) % 3];
-      const double w = weights[f];
-      const uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
-      e.push_back({key, {a < b ? w : -w, std::fabs(w)}});
-    }
-  std::sort(e.begin(), e.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-  bool closed = t->nt > 0;
-  for (size_t i = 0; i < e.size() && closed;) {
-    size_t j = i;
-    double sum = 0.0, mag = 0.0;
-    for (; j < e.size() && e[j].first == e[i].first; ++j) {
-      sum += e[j].second.first;
-      mag += e[j].second.second;
-    }
-    if (std::fabs(sum) > 1e-6 * mag) closed = false;
-    i = j;
-  }
+  bool closed = false;
+  const Check c = weights_close(t->faces_in, weights, t->nt, &closed);
+  if (c.st != DM_OK) return fail(c.st, "%s", c.msg.c_str());
   std::vector<float> ws((size_t)t->nt);
   for (int i = 0; i < t->nt; ++i) ws[(size_t)i] = weights[t->src[(size_t)i]];
   if (!t->weights) {
@@ -1337,10 +1326,11 @@ dm_status dm_band_size(dm_handle* h, const dm_grid* g, const dm_psf* psf, int64_
   DM_TRY(check_psf(psf));
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)stream;
-  DM_TRY(begin_call(h, s));
+  CallScope call(h, s);
+  DM_TRY(call.begin());
   BandDev b;
   DM_TRY(get_band(h, g, psf, s, &b));
-  DM_TRY(end_call(h, s));
+  DM_TRY(call.end());
   *n_entries = b.n_entries;
   return DM_OK;
 }
@@ -1353,7 +1343,8 @@ dm_status dm_band_export(dm_handle* h, const dm_grid* g, const dm_psf* psf, int3
   DM_TRY(check_psf(psf));
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)stream;
-  DM_TRY(begin_call(h, s));
+  CallScope call(h, s);
+  DM_TRY(call.begin());
   BandDev b;
   DM_TRY(get_band(h, g, psf, s, &b));
   const int64_t n = b.n_entries;
@@ -1375,7 +1366,7 @@ dm_status dm_band_export(dm_handle* h, const dm_grid* g, const dm_psf* psf, int3
       if (weight_out) weight_out[i] = w[i];
     }
   }
-  DM_TRY(end_call(h, s));
+  DM_TRY(call.end());
   return DM_OK;
 }
 
@@ -1443,7 +1434,8 @@ dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* st
   if (n == 0) return DM_OK;
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)stream;
-  DM_TRY(begin_call(h, s));
+  CallScope call(h, s);
+  DM_TRY(call.begin());
   std::vector<ReqPlan> P((size_t)n);
   int planned = 0;
   dm_status st = DM_OK;
@@ -1457,10 +1449,10 @@ dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* st
     layout_batch(P, L);
     st = ensure_ws(h, L.total);
   }
-  if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(h->ws), s);
+  if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(h->ws), s, &h->aux);
   for (int i = 0; i < planned; ++i) unpin_band(h, &P[i].g, &P[i].psf);
   if (st != DM_OK) return st;
-  return end_call(h, s);
+  return call.end();
 }
 
 dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev, int64_t n,
@@ -1477,10 +1469,11 @@ dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g,
   const int mode = g->mode;
   const GridC gc = make_gridc(g);
   const int nt = mesh->topo->nt;
-  DM_TRY(begin_call(h, s));
+  CallScope call(h, s);
+  DM_TRY(call.begin());
   if (nt == 0) {
     DM_TRY(zero_fill(out_dev, 2 * n, s));
-    return end_call(h, s);
+    return call.end();
   }
   const SweepPlan sp = plan_fwd(n, nt);
   const int prep_blocks = mesh_prep_blocks(nt);
@@ -1501,7 +1494,7 @@ dm_status dm_mesh_transform(dm_handle* h, const dm_mesh* mesh, const dm_grid* g,
   HIP_TRY(launch_fwd_lanes(mode, kf, n, rec, nt, sp.per_chunk, sp.n_chunks, part, s));
   tm.done();
   HIP_TRY(launch_points_finalize(mode, gc, kf, n, part, sp.n_chunks, info, reinterpret_cast<float2*>(out_dev), s));
-  return end_call(h, s);
+  return call.end();
 }
 
 dm_status dm_mesh_transform_noalloc(dm_handle* h, const dm_mesh* mesh, const dm_grid* g, const int32_t* k_dev,
@@ -1542,10 +1535,11 @@ dm_status dm_mesh_transform_noalloc(dm_handle* h, const dm_mesh* mesh, const dm_
   if (need > DM_NOALLOC_SCRATCH_BYTES)
     return fail(DM_ERR_BUDGET, "%d triangles and %lld frequencies need %zu bytes of scratch; it holds %zu", nt,
                 (long long)n, need, (size_t)DM_NOALLOC_SCRATCH_BYTES);
-  DM_TRY(begin_call(h, s));
+  CallScope call(h, s);
+  DM_TRY(call.begin());
   if (nt == 0) {
     DM_TRY(zero_fill(out_dev, 2 * n, s));
-    return end_call(h, s);
+    return call.end();
   }
   float* rec = reinterpret_cast<float*>(base + o_rec);
   MeshInfo* info = reinterpret_cast<MeshInfo*>(base + o_info);
@@ -1557,7 +1551,7 @@ dm_status dm_mesh_transform_noalloc(dm_handle* h, const dm_mesh* mesh, const dm_
   float2* part = reinterpret_cast<float2*>(base + o_part);
   HIP_TRY(launch_fwd_lanes(mode, kf, n, rec, nt, sp.per_chunk, sp.n_chunks, part, s));
   HIP_TRY(launch_points_finalize(mode, gc, kf, n, part, sp.n_chunks, info, reinterpret_cast<float2*>(out_dev), s));
-  return end_call(h, s);
+  return call.end();
 }
 
 }  // extern "C"
@@ -1602,6 +1596,7 @@ struct dm_server {
   dm_server_config cfg{};
   bool pools = true;
   std::vector<hipStream_t> streams;
+  std::vector<AuxStream> aux;              // each slot's second stream (large requests)
   std::vector<bool> busy;
   std::vector<hipEvent_t> event_pool;
   std::mutex hmu;                          // serialises use of the handle
@@ -1694,7 +1689,7 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
     }
     ReqPlan pl;
     fill_plan(pl, *rq);
-    dm_status st = plan_request(h, pl, s, true);
+    dm_status st = plan_request(h, pl, s, true, BATCH_DIRECT_PAIRS);
     if (st != DM_OK) {
       failed.push_back({take[i], st});
       continue;
@@ -1744,7 +1739,7 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
     void* mem = nullptr;
     hipError_t e = S->pools ? hipMallocAsync(&mem, L.total, s) : hipMalloc(&mem, L.total);
     if (e != hipSuccess) st = fail(DM_ERR_DEVICE, "workspace allocation: %s", hipGetErrorString(e));
-    if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(mem), s, &b.req_ev);
+    if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(mem), s, &S->aux[(size_t)slot], &b.req_ev);
     if (S->pools && mem) (void)hipFreeAsync(mem, s);
     if (!S->pools) b.mem = mem;
     if (S->event_pool.empty()) {
@@ -1844,6 +1839,7 @@ dm_status dm_server_create(int device, const dm_server_config* cfg, dm_server** 
       return fail(DM_ERR_DEVICE, "stream creation failed");
     }
     S->streams.push_back(st);
+    S->aux.push_back(AuxStream{});
     S->busy.push_back(false);
   }
   dm_server* raw = S.release();
@@ -1865,6 +1861,7 @@ dm_status dm_server_destroy(dm_server* S) {
     DeviceGuard dg(S->h->device);
     (void)hipDeviceSynchronize();
     for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
+    for (AuxStream& a : S->aux) destroy_aux(&a);
     for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
     for (auto& kv : S->meshes) {
       dm_topology_destroy(kv.second.topo);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dm_topo.h"   // strip flags, neighbour-table width
+
 namespace dm {
 
 // Per-call mesh quantities computed on the device by the mesh-prep kernels.
@@ -46,9 +48,6 @@ struct BandDev {
 //           of the closed form folded in);  SURFACE: [12] = 2 A_T
 //  [15] 1 for the first triangle of a strip, else 0
 constexpr int TRI_REC = 16;
-// Per-triangle flags of the strip order.
-constexpr int TRI_STRIP_START = 1;   // first triangle of a strip
-constexpr int TRI_REVERSED = 2;      // strip order is an odd permutation of the input face
 constexpr float PHASE_GRID = 4096.0f;   // 2^12
 
 // Band-entry record of the VJP sweeps: ERC float4 per entry,
@@ -62,6 +61,11 @@ constexpr int ERC = 3;
 constexpr int VJP_J_MAX = 8;
 constexpr int vjp_j(int mode) { return mode == 0 ? 5 : 6; }
 constexpr int vjp_chunk(int mode) { return 256 * vjp_j(mode); }
+// Fused forward and gradient sweep (given cotangent): one entry per lane fewer
+// than the gradient sweep, for the forward sums each entry carries; blocks of
+// one chunk of fused_chunk(mode) entries.
+constexpr int fused_j(int mode) { return mode == 0 ? 4 : 4; }
+constexpr int fused_chunk(int mode) { return 256 * fused_j(mode); }
 // Forward sweep: FWD_J band entries per lane, FWD_CHUNK entries per block.
 constexpr int FWD_J = 3;
 constexpr int FWD_CHUNK = 256 * FWD_J;
@@ -70,14 +74,18 @@ static_assert(FWD_J <= 8 && VJP_J_MAX <= 8, "queued pairs store the entry step i
 // Work item of the persistent batched sweeps: one tile of one request's
 // forward sweep (kind 0: FWD_CHUNK band entries from x0, triangle chunk c) or
 // gradient sweep (kind 1: entry chunk c of epc entries, triangles x0.. x0+vtpb).
+// The fused sweep's tiles need no items (see launch_batch_sweep).
 struct SweepItem {
   int kind, req, x0, c;
 };
 
-// Per-request pointers and chunking for the batched sweep.
+// Per-request pointers and chunking for the batched sweep.  Fused requests:
+// tile0 is the request's first tile in its launch and ntr its triangle ranges
+// of vtpb triangles per entry chunk of fused_chunk(mode) entries.
 struct SweepReq {
-  int mode, nE, nt, tpc, epc, vsub, vtpb, pad;
-  float tpx, tpy, tpz, pad2;   // 2 pi / L (SURFACE gradient)
+  int mode, nE, nt, tpc, epc, vsub, vtpb, tile0;
+  float tpx, tpy, tpz;   // 2 pi / L (SURFACE gradient)
+  int ntr;
   const float4* kf;
   const float* rec;
   float2* fpart;       // [fwd chunks][nE]
@@ -88,12 +96,17 @@ struct SweepReq {
 constexpr int SWEEP_THREADS = 256;
 
 // ---- launchers (defined in dm_kernels.hip); all enqueue on `s` ----
-// Up to four persistent launches over the items sorted into groups
-// (forward volume, forward surface, gradient volume, gradient surface);
-// group g is items [group_end[g-1], group_end[g]).  counters[0..3] are zeroed
-// first.
-hipError_t launch_batch_sweep(const SweepItem* items, const int* group_end, const SweepReq* reqs, int* counters,
-                              hipStream_t s);
+// The persistent launches of a batch.  Groups 0-3 (2 kind + mode: forward
+// volume, forward surface, gradient volume, gradient surface) run the sorted
+// items, group g being items [group_end[g-1], group_end[g]).  Groups 4 and 5
+// run the fused tiles of each density: fused_reqs[m] lists n_fused_reqs[m]
+// requests, request r owning tiles [tile0_r, tile0_{r+1}) of the
+// n_fused_tiles[m] (entry chunk major, ntr triangle ranges per chunk), handed
+// out in increasing order.  counters[0..BATCH_GROUPS) are zeroed first.
+constexpr int BATCH_GROUPS = 6;
+hipError_t launch_batch_sweep(const SweepItem* items, const int* group_end, const SweepReq* reqs,
+                              const SweepReq* const* fused_reqs, const int* n_fused_reqs, const int* n_fused_tiles,
+                              int* counters, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_band_count(const GridC& g, const double* sigma6, double qmax, int32_t* cnt, int64_t n_slots,
                              hipStream_t s);
@@ -139,6 +152,13 @@ constexpr int VJP_TPB_MAX = 256;
 hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,
                             int chunks_per_block, int n_chunks, const float4* erec, int64_t nE, float* part,
                             hipStream_t s);
+// Fused sweep: ceil(nE / fused_chunk(mode)) x ceil(nt / tris_per_block) blocks;
+// gradient partials part[entry block][NC][nt] (as launch_vjp_lanes with one
+// chunk per block) and forward partials fpart[triangle block][nE] (as
+// launch_fwd_lanes).  The volume density needs the record's normal (as both
+// sweeps do).
+hipError_t launch_fused_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,
+                              const float4* erec, int64_t nE, float* part, float2* fpart, hipStream_t s);
 int vjp_reduce_groups(int n_chunks);
 hipError_t launch_vjp_reduce(int mode, const float* part, int n_chunks, int nt, float* tmp, float* red,
                              hipStream_t s);
@@ -155,16 +175,20 @@ hipError_t launch_points_finalize(int mode, const GridC& g, const float4* kf, in
 
 inline int nchannels(int mode) { return mode == 0 ? 3 : 10; }
 
-// Smoothed gradient (I + lam L)^{-2} g of the shape step (dm_precond.hip):
-// one workgroup, CG on the vertex adjacency (CSR, and when every degree is at
-// most LAP_TABLE_W also a table [nv][LAP_TABLE_W] of neighbours padded with
-// -1, else adj_tab = nullptr); ws holds laplace_smooth_workspace(nv) bytes;
-// info (device, optional) receives {iterations, relative residual} of each
-// of the two solves.
-constexpr int LAP_TABLE_W = 8;
+// Smoothed gradient (I + lam L)^{-2} g of the shape step (dm_precond.hip).
+// Meshes of at most 3072 vertices whose degrees fit the neighbour table
+// (adj_tab [nv][LAP_TABLE_W], -1 padded; nullptr when a degree exceeds it):
+// one workgroup runs Jacobi-preconditioned CG with the vectors resident on
+// the chip.  Larger meshes: Chebyshev iteration, one launch per step, over
+// the table or the CSR lists (adj_off, adj_nbr), mu >= the largest eigenvalue
+// of L (the largest d_i + d_j over the edges).  ws holds
+// laplace_smooth_workspace(nv) bytes; info (device, optional) receives
+// {iterations, relative residual} of each of the two solves.
 size_t laplace_smooth_workspace(int nv);
+// Chebyshev steps that bound each column's relative residual by tol (at most max_iter; 0: the identity).
+int chebyshev_steps(float lam, int mu, float tol, int max_iter);
 hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, const int32_t* adj_tab,
-                                 float lam, const float* g, float* out, float* ws, int max_iter, float tol,
+                                 int mu, float lam, const float* g, float* out, float* ws, int max_iter, float tol,
                                  float* info, hipStream_t s);
 
 // Fixed scratch of the allocation-free entry point (dm_scratch.hip):

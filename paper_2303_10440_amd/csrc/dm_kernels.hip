@@ -85,6 +85,14 @@ __device__ __forceinline__ float vertex3_phase(float kx, float ky, float kz, con
   th -= __builtin_rintf(th);
   return th + fmaf(kz, r[5], fmaf(ky, r[4], kx * r[3]));
 }
+// frac(w - k.u3) in [0, 1): the fraction of the exact grid part (v_fract is
+// exact there), then the rest, with w (a phase in revolutions, e.g. the
+// adjoint weight's) folded into it.
+__device__ __forceinline__ float vertex3_wphase(float kx, float ky, float kz, const float* r, float w) {
+  const float th = fmaf(kz, r[2], fmaf(ky, r[1], kx * r[0]));   // exact: 12-bit grid part
+  const float lo = fmaf(kz, r[5], fmaf(ky, r[4], fmaf(kx, r[3], -w)));
+  return __builtin_amdgcn_fractf(__builtin_amdgcn_fractf(-th) - lo);
+}
 __device__ __forceinline__ void rel_phases(float kx, float ky, float kz, const float* r, float& d2, float& d3) {
   d2 = fmaf(kz, r[8], fmaf(ky, r[7], kx * r[6]));
   d3 = fmaf(kz, r[11], fmaf(ky, r[10], kx * r[9]));
@@ -178,6 +186,7 @@ __device__ __forceinline__ void dd3_acc(float t1, float d2, float d3, float w, f
 // One pair of the gradient sweep: with W the adjoint weight of the frequency,
 //   VOLUME:  z[p]  = Re(W DD4_p)            (p over the slots {node 0, d2, d3})
 //   SURFACE: wf    = Re(W f_T), z[p] = Im(W DD4_p)
+// and in both modes fr + i fi = f_T (the fused sweep's forward value).
 // DD4_p is the divided difference with node p repeated (Eq. 10 up to -i xi).
 // Stable branch (sorted nodes, R = i/S, P_x = e^{-2 pi i t_x} the vertex phases,
 // phi1, phi2 the first two phi-functions at -i Gamma_j):
@@ -189,7 +198,7 @@ __device__ __forceinline__ void dd3_acc(float t1, float d2, float d3, float w, f
 // the two kinds of pairs apart, so each pass runs one scheme only.
 template <int MODE>
 __device__ __forceinline__ void vjp_pair_series(float t1, float d2, float d3, float wr, float wi, float& wf,
-                                                float z[3]) {
+                                                float z[3], float& fr, float& fi) {
   {
     const float m = (d2 + d3) * (1.0f / 3.0f);
     const float a[3] = {-TWO_PI_F * m, TWO_PI_F * (d2 - m), TWO_PI_F * (d3 - m)};
@@ -207,6 +216,8 @@ __device__ __forceinline__ void vjp_pair_series(float t1, float d2, float d3, fl
     // WG = W e^{-2 pi i (t1 + m)}
     const float gr = wr * c - wi * sn, gi = fmaf(wr, sn, wi * c);
     if (MODE == 1) wf = gr * pre - gi * pim;
+    fr = c * pre - sn * pim;
+    fi = fmaf(c, pim, sn * pre);
     const float third_re = pre * (1.0f / 3.0f), third_im = pim * (1.0f / 3.0f);
     const float e2_23 = E2 * (2.0f / 3.0f);
 #pragma unroll
@@ -221,7 +232,7 @@ __device__ __forceinline__ void vjp_pair_series(float t1, float d2, float d3, fl
 
 template <int MODE>
 __device__ __forceinline__ void vjp_pair_sorted(float t1, float d2, float d3, float wr, float wi, float& wf,
-                                                float z[3]) {
+                                                float z[3], float& fr, float& fi) {
   const float lo = fminf(fminf(0.0f, d2), d3);
   const float hi = fmaxf(fmaxf(0.0f, d2), d3);
   const float s = hi - lo;
@@ -263,7 +274,8 @@ __device__ __forceinline__ void vjp_pair_sorted(float t1, float d2, float d3, fl
   // F0 = P_mid phi1_2 - P_lo phi1_1 ; f = (i/S) F0
   const float F0r = (pmr * q2r - pmi * q2i) - (plr * q1r - pli * q1i);
   const float F0i = fmaf(pmr, q2i, pmi * q2r) - fmaf(plr, q1i, pli * q1r);
-  const float fr = -F0i * q.invS, fi = F0r * q.invS;
+  fr = -F0i * q.invS;
+  fi = F0r * q.invS;
   // W' = W (i/S)
   const float Wr = -wi * q.invS, Wi = wr * q.invS;
   if (MODE == 1) wf = wr * fr - wi * fi;
@@ -725,7 +737,7 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
     float a, b;
     rel_phases(kx[j], ky[j], kz[j], r, a, b);
     // e^{-2 pi i t} = (cos 2 pi q, sin 2 pi q) at q = -t: no negation of the sine
-    const float q3 = wrap(-vertex3_phase(kx[j], ky[j], kz[j], r));
+    const float q3 = vertex3_wphase(kx[j], ky[j], kz[j], r, 0.0f);
     const float Nr = __builtin_amdgcn_cosf(q3), Ni = __builtin_amdgcn_sinf(q3);
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
@@ -1075,19 +1087,23 @@ constexpr int VJP_TB = 32;   // triangles between block-level merges
 
 // Queued pairs per wave and ring (power of two): at most 63 left from earlier
 // triangles plus 64 J from the current one.
-template <int MODE>
+template <int J>
 constexpr int vjp_ring() {
-  return 64 + 64 * vjp_j(MODE) <= 512 ? 512 : 1024;
+  return 64 + 64 * J <= 512 ? 512 : 1024;
 }
 static_assert(64 + 64 * VJP_J_MAX <= 1024, "ring too small");
 
 // Two rings per wave: ring 0 holds pairs for the series (node spread below
-// one radian), ring 1 pairs for the sorted scheme.
-template <int MODE>
+// one radian), ring 1 pairs for the sorted scheme.  The fused sweep (FWD)
+// keeps in fb the forward values of its queued pairs, one slot per entry, and
+// writes each block's merged per-triangle sums straight out (its blocks own one
+// entry chunk), so it has no per-block sum table.
+template <int MODE, int J, bool FWD>
 struct VjpLds {
-  uint16_t queue[4][2][vjp_ring<MODE>()];
+  uint16_t queue[4][2][vjp_ring<J>()];
   float tot[4][4][VJP_TB][MODE == 0 ? 3 : 10];   // [wave][row of 16 lanes][triangle][channel]
-  float sum[VJP_TPB_MAX][10];
+  float sum[FWD ? 1 : VJP_TPB_MAX][MODE == 0 ? 3 : 10];
+  float2 fb[4][FWD ? 64 * J : 1];   // [wave][entry offset 64 j + lane]
 };
 
 // Head, tail and end of the previous triangle's pairs in one ring.
@@ -1099,48 +1115,73 @@ struct VjpRing {
 // the adjoint weight's phase folded in (G_p = e^{-2 pi i (t_p - phi_W)}) and
 // the relative phases a, b (see lag_pair for the formulas).  With use false
 // every output is exactly zero (the common factor 1 / (2 pi a b c) is
-// replaced by zero, so a vanishing gap cannot produce inf or NaN).
-template <int MODE>
+// replaced by zero, so a vanishing gap cannot produce inf or NaN).  With AMP
+// the weight's modulus is folded into the Lagrange coefficients; without it
+// the outputs are those of a unit modulus (the caller scales them) and
+//   wf + i Pi = sum_p k_p G_p = e^{2 pi i phi_W} f_T,
+// the forward value of the pair in the weight's phase frame.
+template <int MODE, bool AMP>
 __device__ __forceinline__ void lag_pair_g(float a, float b, bool use, float amp, float G0r, float G0i, float G1r,
-                                           float G1i, float G2r, float G2i, float& wf, float z[3]) {
+                                           float G1i, float G2r, float G2i, float& wf, float z[3], float& Pi) {
   const float c = b - a;
   const float ab = a * b;
   const float rD = use ? __builtin_amdgcn_rcpf(ab * c) * INV_TWO_PI_F : 0.0f;   // 1 / (2 pi a b c)
   const float al = b * c * rD, be = a * c * rD, ga = ab * rD;
-  const float alw = amp * al;
-  const float k0 = -alw * be, k1 = alw * ga, k2 = -amp * (be * ga);
+  float k0, k1, k2;
+  if (AMP) {
+    const float alw = amp * al;
+    k0 = -alw * be;
+    k1 = alw * ga;
+    k2 = -amp * (be * ga);
+  } else {
+    k0 = -(al * be);
+    k1 = al * ga;
+    k2 = -(be * ga);
+  }
   const float R0 = k0 * G0r, I0 = k0 * G0i, R1 = k1 * G1r, I1 = k1 * G1i, R2 = k2 * G2r, I2 = k2 * G2i;
   const float s01 = al + be, s21 = ga - al, s12 = be + ga;
+  wf = R0 + R1 + R2;
+  Pi = I0 + I1 + I2;
   if (MODE == 0) {
     z[0] = fmaf(-s01, I0, fmaf(-al, I1, fmaf(-be, I2, R0)));
     z[1] = fmaf(-s21, I1, fmaf(al, I0, fmaf(-ga, I2, R1)));
     z[2] = fmaf(s12, I2, fmaf(be, I0, fmaf(ga, I1, R2)));
   } else {
-    wf = R0 + R1 + R2;
     z[0] = fmaf(s01, R0, fmaf(al, R1, fmaf(be, R2, I0)));
     z[1] = fmaf(s21, R1, fmaf(-al, R0, fmaf(ga, R2, I1)));
     z[2] = fmaf(-s12, R2, fmaf(-be, R0, fmaf(-ga, R1, I2)));
   }
 }
 
+// The gradient sweep folds the adjoint weight's modulus into the Lagrange
+// coefficients where that is cheaper; the volume density and the fused sweep
+// scale the outputs instead (the fused sweep needs the unscaled forward value).
+template <int MODE, bool FWD>
+constexpr bool vjp_amp_in_coeffs() {
+  return MODE == 1 && !FWD;
+}
+
 // Closed-form pairs of one triangle: X holds the weighted phase factors of
 // vertex 1, Y of vertex 2 (computed here at a strip start); on return X holds
 // those of vertex 3, so the next triangle of the strip swaps X and Y.  Pairs
 // that need the stable scheme are appended to the wave's ring of queued pairs
-// (ring positions tail.., tagged with the triangle's parity).
-template <int MODE, bool OPQ>
-__device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int tag, const float (&kx)[vjp_j(MODE)],
-                                               const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
-                                               const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
-                                               float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
-                                               float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)], float tpx,
-                                               float tpy, float tpz, int lane, uint16_t (*ring)[vjp_ring<MODE>()],
+// (ring positions tail.., tagged with the triangle's parity).  The fused sweep
+// (FWD) also adds the pair's forward value, weighted like the forward sweep's
+// (k.n with the closed form's 1/(4 pi^2) for the volume density, 2A for the
+// surface density), to Fr + i Fi in the weight's phase frame.
+template <int MODE, int J, bool FWD, bool OPQ>
+__device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int tag, const float (&kx)[J],
+                                               const float (&ky)[J], const float (&kz)[J], const float (&amp)[J],
+                                               const float (&phw)[J], float (&Xr)[J], float (&Xi)[J], float (&Yr)[J],
+                                               float (&Yi)[J], float (&Fr)[J], float (&Fi)[J], float tpx, float tpy,
+                                               float tpz, int lane, uint16_t (*ring)[vjp_ring<J>()],
                                                VjpRing (&rq)[2], float (&acc)[MODE == 0 ? 3 : 10]) {
-  constexpr int J = vjp_j(MODE);
-  float rvg[12];
+  constexpr bool AMP = vjp_amp_in_coeffs<MODE, FWD>();
+  constexpr int NR = MODE == 0 ? (FWD ? 15 : 12) : 12;
+  float rvg[NR];
   if (MODE == 0) {
 #pragma unroll
-    for (int i = 0; i < 12; ++i) rvg[i] = to_vgpr(r[i]);
+    for (int i = 0; i < NR; ++i) rvg[i] = to_vgpr(r[i]);
   }
   const float* rv = MODE == 0 ? rvg : r;
   if (start) {
@@ -1160,21 +1201,28 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
   for (int j = 0; j < J; ++j) {
     float a, b;
     rel_phases(kx[j], ky[j], kz[j], rv, a, b);
-    const float q3 = wrap(phw[j] - vertex3_phase(kx[j], ky[j], kz[j], rv));
+    const float q3 = vertex3_wphase(kx[j], ky[j], kz[j], rv, phw[j]);
     const float Nr = __builtin_amdgcn_cosf(q3), Ni = __builtin_amdgcn_sinf(q3);
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
     const bool close = mn < LAG_GAP, small = mx < SERIES_REV;
     const bool fast = !close && !small;
-    float wf = 0.0f, z[3];
-    lag_pair_g<MODE>(a, b, fast, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z);
+    float wf = 0.0f, z[3], Pi;
+    lag_pair_g<MODE, AMP>(a, b, fast, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z, Pi);
     if (MODE == 0) {
 #pragma unroll
-      for (int p = 0; p < 3; ++p) acc[p] += z[p];
+      for (int p = 0; p < 3; ++p) acc[p] = fmaf(amp[j], z[p], acc[p]);
     } else {
-      const float x0 = kx[j] * tpx, x1 = ky[j] * tpy, x2 = kz[j] * tpz;
-      acc[0] += wf;
+      float x0 = kx[j] * tpx, x1 = ky[j] * tpy, x2 = kz[j] * tpz;
+      if (AMP) {
+        acc[0] += wf;
+      } else {
+        acc[0] = fmaf(amp[j], wf, acc[0]);
+        x0 *= amp[j];
+        x1 *= amp[j];
+        x2 *= amp[j];
+      }
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         const float zp = z[p];
@@ -1182,6 +1230,11 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
         acc[2 + 3 * p] = fmaf(zp, x1, acc[2 + 3 * p]);
         acc[3 + 3 * p] = fmaf(zp, x2, acc[3 + 3 * p]);
       }
+    }
+    if (FWD) {
+      const float wt = MODE == 0 ? fmaf(kz[j], rv[14], fmaf(ky[j], rv[13], kx[j] * rv[12])) : r[12];
+      Fr[j] = fmaf(wt, wf, Fr[j]);
+      Fi[j] = fmaf(wt, Pi, Fi[j]);
     }
     // Ballots of plain compares are the compares' own lane masks.  Lanes past
     // the end of the band (all phases 0) are queued too and skipped by the
@@ -1192,7 +1245,7 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
       if (small) {
         const int pos = rq[0].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bs >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bs, 0u));
-        ring[0][pos & (vjp_ring<MODE>() - 1)] = OPQ ? queue_item(tag, j, lane) : plain_item(tag, j, lane);
+        ring[0][pos & (vjp_ring<J>() - 1)] = OPQ ? queue_item(tag, j, lane) : plain_item(tag, j, lane);
       }
       rq[0].tail += __popcll(bs);
     }
@@ -1200,7 +1253,7 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
       if (close && !small) {
         const int pos = rq[1].tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bc >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bc, 0u));
-        ring[1][pos & (vjp_ring<MODE>() - 1)] = OPQ ? queue_item(tag, j, lane) : plain_item(tag, j, lane);
+        ring[1][pos & (vjp_ring<J>() - 1)] = OPQ ? queue_item(tag, j, lane) : plain_item(tag, j, lane);
       }
       rq[1].tail += __popcll(bc);
     }
@@ -1213,26 +1266,31 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
 // position head, on full waves: pairs tagged cur_tag belong to triangle r_cur
 // (sums into acc_cur), the others to the previous triangle r_prev (acc_prev).
 // erec_w points at the wave's first entry; n_w of its entries lie in the band
-// (queued entries past them are skipped).
-template <int MODE, int KIND>
+// (queued entries past them are skipped).  The fused sweep (FWD) adds each
+// pair's weighted forward value to its entry's slot of fb, the pairs of the
+// current triangle first, then those of the previous one (an entry is queued
+// at most once per triangle), so no two lanes update one slot at once.
+template <int MODE, int J, int KIND, bool FWD>
 __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, int n, const float* r_cur,
                                                const float* r_prev, int cur_tag, const float4* __restrict__ erec_w,
                                                int n_w, int lane, float (&acc_cur)[MODE == 0 ? 3 : 10],
-                                               float (&acc_prev)[MODE == 0 ? 3 : 10]) {
+                                               float (&acc_prev)[MODE == 0 ? 3 : 10], float2* fb) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   wave_lds_sync();
-  const int it = lane < n ? ring[(head + lane) & (vjp_ring<MODE>() - 1)] : 0;
+  const int it = lane < n ? ring[(head + lane) & (vjp_ring<J>() - 1)] : 0;
   const int eo = 64 * ((it >> 6) & 7) + (it & 63);   // entry offset within the wave's 64 J
+  float ffr = 0.0f, ffi = 0.0f;
+  bool fact = false, fcur = false;
   if (lane < n && eo < n_w) {
     const bool cur = (it >> 9) == cur_tag;
     const float* r = cur ? r_cur : r_prev;
     const float4 A = erec_w[ERC * eo], B = erec_w[ERC * eo + 1];
-    float tv, a, b, wf = 0.0f, z[3];
+    float tv, a, b, wf = 0.0f, z[3], fr, fi;
     tri_phases(A.x, A.y, A.z, r, tv, a, b);
     if (KIND == 0)
-      vjp_pair_series<MODE>(tv, a, b, A.w, B.x, wf, z);
+      vjp_pair_series<MODE>(tv, a, b, A.w, B.x, wf, z, fr, fi);
     else
-      vjp_pair_sorted<MODE>(tv, a, b, A.w, B.x, wf, z);
+      vjp_pair_sorted<MODE>(tv, a, b, A.w, B.x, wf, z, fr, fi);
     float add[NC];
     if (MODE == 0) {
 #pragma unroll
@@ -1251,14 +1309,32 @@ __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, i
       acc_cur[ch] += cur ? add[ch] : 0.0f;
       acc_prev[ch] += cur ? 0.0f : add[ch];
     }
+    if (FWD) {
+      const float wt =
+          MODE == 0 ? fmaf(A.z, r[14], fmaf(A.y, r[13], A.x * r[12])) * FOUR_PI2_F : r[12];
+      ffr = wt * fr;
+      ffi = wt * fi;
+      fact = true;
+      fcur = cur;
+    }
+  }
+  if (FWD) {
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+      if (fact && fcur == (ph == 0)) {
+        float2& s = fb[eo];
+        s = make_float2(s.x + ffr, s.y + ffi);
+      }
+      wave_lds_sync();
+    }
   }
 }
 
-// Row sums (16 lanes each) of one triangle into L.tot[w][row][tt]; the block
+// Row sums (16 lanes each) of one triangle into tot[w][row][tt]; the block
 // merge adds the 4 rows of the 4 waves.
 template <int MODE>
 __device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3 : 10], int tt, int lane, int w,
-                                                VjpLds<MODE>& L) {
+                                                float (*tot)[4][VJP_TB][MODE == 0 ? 3 : 10]) {
   constexpr int NC = MODE == 0 ? 3 : 10;
   float v[NC];
 #pragma unroll
@@ -1266,23 +1342,24 @@ __device__ __forceinline__ void vjp_lanes_close(const float (&acc)[MODE == 0 ? 3
   // one store block, so the channels go out as wide LDS writes
   if ((lane & 15) == 0) {
 #pragma unroll
-    for (int ch = 0; ch < NC; ++ch) L.tot[w][lane >> 4][tt][ch] = v[ch];
+    for (int ch = 0; ch < NC; ++ch) tot[w][lane >> 4][tt][ch] = v[ch];
   }
 }
 
 // Passes over ring KIND: full ones while 64 pairs are queued, then a partial
 // one only if pairs of the previous triangle are still queued.
-template <int MODE, int KIND>
+template <int MODE, int J, int KIND, bool FWD>
 __device__ __forceinline__ void vjp_lanes_drain(VjpRing& q, const uint16_t* ring, bool prev_open, const float* r,
                                                 const float* r_prev, int tag, const float4* __restrict__ erec_w,
                                                 int n_w, int lane, float (&acc)[MODE == 0 ? 3 : 10],
-                                                float (&acc_prev)[MODE == 0 ? 3 : 10]) {
+                                                float (&acc_prev)[MODE == 0 ? 3 : 10], float2* fb) {
   while (q.tail - q.head >= 64) {
-    vjp_lanes_pass<MODE, KIND>(ring, q.head, 64, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
+    vjp_lanes_pass<MODE, J, KIND, FWD>(ring, q.head, 64, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev, fb);
     q.head += 64;
   }
   if (prev_open && q.head < q.prev_end) {
-    vjp_lanes_pass<MODE, KIND>(ring, q.head, q.tail - q.head, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
+    vjp_lanes_pass<MODE, J, KIND, FWD>(ring, q.head, q.tail - q.head, r, r_prev, tag, erec_w, n_w, lane, acc,
+                                       acc_prev, fb);
     q.head = q.tail;
   }
 }
@@ -1292,28 +1369,31 @@ __device__ __forceinline__ void vjp_lanes_drain(VjpRing& q, const uint16_t* ring
 // finished by partial passes only where some of its pairs are still queued, so
 // most passes are full.  A triangle is closed (reduced into L.tot) once none
 // of its pairs is queued in either ring.
-template <int MODE, bool OPQ>
-__device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int tt, const float (&kx)[vjp_j(MODE)],
-                                               const float (&ky)[vjp_j(MODE)], const float (&kz)[vjp_j(MODE)],
-                                               const float (&amp)[vjp_j(MODE)], const float (&phw)[vjp_j(MODE)],
-                                               float (&Xr)[vjp_j(MODE)], float (&Xi)[vjp_j(MODE)],
-                                               float (&Yr)[vjp_j(MODE)], float (&Yi)[vjp_j(MODE)],
+template <int MODE, int J, bool FWD, bool OPQ>
+__device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int tt, const float (&kx)[J],
+                                               const float (&ky)[J], const float (&kz)[J], const float (&amp)[J],
+                                               const float (&phw)[J], float (&Xr)[J], float (&Xi)[J], float (&Yr)[J],
+                                               float (&Yi)[J], float (&Fr)[J], float (&Fi)[J],
                                                const float4* __restrict__ erec_w, int n_w, float tpx, float tpy,
-                                               float tpz, int lane, int w, VjpLds<MODE>& L, VjpRing (&rq)[2],
+                                               float tpz, int lane, int w, VjpLds<MODE, J, FWD>& L, VjpRing (&rq)[2],
                                                bool& prev_open, const float*& r_prev,
                                                float (&acc_prev)[MODE == 0 ? 3 : 10]) {
   constexpr int NC = MODE == 0 ? 3 : 10;
+  // -0 is the additive identity (-0 + x == x for every x), so the first
+  // additions fold away
   float acc[NC];
 #pragma unroll
-  for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0f;
+  for (int ch = 0; ch < NC; ++ch) acc[ch] = -0.0f;
   const int tag = tt & 1;
-  vjp_lanes_main<MODE, OPQ>(r, start, tag, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi, tpx, tpy, tpz, lane, L.queue[w],
-                       rq, acc);
-  vjp_lanes_drain<MODE, 0>(rq[0], L.queue[w][0], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
-  vjp_lanes_drain<MODE, 1>(rq[1], L.queue[w][1], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev);
-  if (prev_open) vjp_lanes_close<MODE>(acc_prev, tt - 1, lane, w, L);
+  vjp_lanes_main<MODE, J, FWD, OPQ>(r, start, tag, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi, Fr, Fi, tpx, tpy, tpz,
+                                    lane, L.queue[w], rq, acc);
+  vjp_lanes_drain<MODE, J, 0, FWD>(rq[0], L.queue[w][0], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev,
+                                   L.fb[w]);
+  vjp_lanes_drain<MODE, J, 1, FWD>(rq[1], L.queue[w][1], prev_open, r, r_prev, tag, erec_w, n_w, lane, acc, acc_prev,
+                                   L.fb[w]);
+  if (prev_open) vjp_lanes_close<MODE>(acc_prev, tt - 1, lane, w, L.tot);
   if (rq[0].head == rq[0].tail && rq[1].head == rq[1].tail) {
-    vjp_lanes_close<MODE>(acc, tt, lane, w, L);
+    vjp_lanes_close<MODE>(acc, tt, lane, w, L.tot);
     prev_open = false;
   } else {
 #pragma unroll
@@ -1325,26 +1405,33 @@ __device__ __forceinline__ void vjp_lanes_step(const float* r, bool start, int t
   }
 }
 
-template <int MODE, bool OPQ = true>
+// A block's tile: n_sub entry chunks of 256 J entries from e_begin times the
+// strip-ordered triangles [t0, t1).  Gradient sweep (FWD false): the
+// per-triangle sums of all its chunks are added in the block's sum table and
+// written to part_out[NC][nt] at the end.  Fused sweep (FWD, n_sub = 1): they
+// are written to part_out after every VJP_TB triangles, and each entry's
+// forward sum over the tile, back in the plain phase frame and with the
+// forward sweep's scaling, goes to fpart_row[entry].
+template <int MODE, int J, bool FWD, bool OPQ = true>
 __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, int nt, int t0, int t1,
                                                const float4* __restrict__ erec, int64_t nE, int64_t e_begin,
                                                int n_sub, float tpx, float tpy, float tpz,
-                                               float* __restrict__ part_out, VjpLds<MODE>& L) {
+                                               float* __restrict__ part_out, float2* __restrict__ fpart_row,
+                                               VjpLds<MODE, J, FWD>& L) {
   constexpr int NC = MODE == 0 ? 3 : 10;
-  constexpr int J = vjp_j(MODE);
   // the wave index is wave-uniform: entry addresses get a scalar base
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int g = 0; g < n_sub; ++g) {
-    const int64_t ew = e_begin + (int64_t)g * vjp_chunk(MODE) + (int64_t)w * 64 * J;
+    const int64_t ew = e_begin + (int64_t)g * 256 * J + (int64_t)w * 64 * J;
     const float4* erec_w = erec + ERC * ew;
     const int n_w = (int)max<int64_t>(0, min<int64_t>(nE - ew, 64 * J));   // entries of this wave in the band
     float kx[J], ky[J], kz[J], amp[J], phw[J];
-    float Xr[J], Xi[J], Yr[J], Yi[J];
+    float Xr[J], Xi[J], Yr[J], Yi[J], Fr[J], Fi[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int64_t e = ew + 64 * j + lane;
       kx[j] = ky[j] = kz[j] = amp[j] = phw[j] = 0.0f;
-      Xr[j] = Xi[j] = Yr[j] = Yi[j] = 0.0f;
+      Xr[j] = Xi[j] = Yr[j] = Yi[j] = Fr[j] = Fi[j] = 0.0f;
       if (e < nE) {
         const float4 A = erec[ERC * e], C = erec[ERC * e + 2];
         kx[j] = A.x;
@@ -1353,6 +1440,7 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
         amp[j] = C.x;
         phw[j] = C.y;
       }
+      if (FWD) L.fb[w][64 * j + lane] = make_float2(0.0f, 0.0f);
     }
     for (int tb = t0; tb < t1; tb += VJP_TB) {
       const int tn = min(VJP_TB, t1 - tb);
@@ -1364,11 +1452,13 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
       for (int ch = 0; ch < NC; ++ch) acc_prev[ch] = 0.0f;
       for (int tt = 0; tt < tn; tt += 2) {
         const float* r = rec + (size_t)(tb + tt) * TRI_REC;
-        vjp_lanes_step<MODE, OPQ>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, Xr, Xi, Yr, Yi,
-                             erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
+        vjp_lanes_step<MODE, J, FWD, OPQ>(r, tb + tt == t0 || r[15] != 0.0f, tt, kx, ky, kz, amp, phw, Xr, Xi, Yr,
+                                          Yi, Fr, Fi, erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev,
+                                          acc_prev);
         if (tt + 1 < tn)
-          vjp_lanes_step<MODE, OPQ>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, Yr, Yi, Xr,
-                               Xi, erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open, r_prev, acc_prev);
+          vjp_lanes_step<MODE, J, FWD, OPQ>(r + TRI_REC, r[TRI_REC + 15] != 0.0f, tt + 1, kx, ky, kz, amp, phw, Yr,
+                                            Yi, Xr, Xi, Fr, Fi, erec_w, n_w, tpx, tpy, tpz, lane, w, L, rq, prev_open,
+                                            r_prev, acc_prev);
       }
       if (prev_open) {
         // only the last triangle (tn - 1) is still open: finish its pairs
@@ -1376,12 +1466,12 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) none[ch] = 0.0f;
         if (rq[0].tail > rq[0].head)
-          vjp_lanes_pass<MODE, 0>(L.queue[w][0], rq[0].head, rq[0].tail - rq[0].head, r_prev, r_prev, (tn & 1), erec_w,
-                                  n_w, lane, none, acc_prev);
+          vjp_lanes_pass<MODE, J, 0, FWD>(L.queue[w][0], rq[0].head, rq[0].tail - rq[0].head, r_prev, r_prev,
+                                          (tn & 1), erec_w, n_w, lane, none, acc_prev, L.fb[w]);
         if (rq[1].tail > rq[1].head)
-          vjp_lanes_pass<MODE, 1>(L.queue[w][1], rq[1].head, rq[1].tail - rq[1].head, r_prev, r_prev, (tn & 1), erec_w,
-                                  n_w, lane, none, acc_prev);
-        vjp_lanes_close<MODE>(acc_prev, tn - 1, lane, w, L);
+          vjp_lanes_pass<MODE, J, 1, FWD>(L.queue[w][1], rq[1].head, rq[1].tail - rq[1].head, r_prev, r_prev,
+                                          (tn & 1), erec_w, n_w, lane, none, acc_prev, L.fb[w]);
+        vjp_lanes_close<MODE>(acc_prev, tn - 1, lane, w, L.tot);
       }
       __syncthreads();
       for (int i = threadIdx.x; i < tn * NC; i += SWEEP_T) {
@@ -1390,15 +1480,38 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
 #pragma unroll
         for (int ww = 0; ww < 4; ++ww)
           v += (L.tot[ww][0][tt][ch] + L.tot[ww][1][tt][ch]) + (L.tot[ww][2][tt][ch] + L.tot[ww][3][tt][ch]);
-        float& acc_t = L.sum[tb - t0 + tt][ch];
-        acc_t = g == 0 ? v : acc_t + v;
+        if (FWD) {
+          part_out[(size_t)ch * nt + tb + tt] = v;
+        } else {
+          float& acc_t = L.sum[tb - t0 + tt][ch];
+          acc_t = g == 0 ? v : acc_t + v;
+        }
       }
       __syncthreads();
     }
+    if (FWD) {
+      // back from the weight's phase frame (multiply by e^{-2 pi i phi_W}); the
+      // volume density's closed form carries 4 pi^2 (the forward sweep's scaling)
+      constexpr float FS = MODE == 0 ? FOUR_PI2_F : 1.0f;
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int64_t e = ew + 64 * j + lane;
+        if (e < nE) {
+          const float q = wrap(phw[j]);
+          const float cq = __builtin_amdgcn_cosf(q), sq = __builtin_amdgcn_sinf(q);
+          const float ur = fmaf(Fr[j], cq, Fi[j] * sq), ui = fmaf(Fi[j], cq, -Fr[j] * sq);
+          const float2 qb = L.fb[w][64 * j + lane];
+          fpart_row[e] = make_float2(fmaf(FS, ur, qb.x), fmaf(FS, ui, qb.y));
+        }
+      }
+    }
   }
-  for (int i = threadIdx.x; i < (t1 - t0) * NC; i += SWEEP_T) {
-    const int tl = i / NC, ch = i - tl * NC;
-    part_out[(size_t)ch * nt + t0 + tl] = n_sub > 0 ? L.sum[tl][ch] : 0.0f;
+  if (!FWD) {
+    for (int i = threadIdx.x; i < (t1 - t0) * NC; i += SWEEP_T) {
+      const int tl = i / NC, ch = i - tl * NC;
+      part_out[(size_t)ch * nt + t0 + tl] = n_sub > 0 ? L.sum[tl][ch] : 0.0f;
+    }
   }
 }
 
@@ -1409,13 +1522,35 @@ template <int MODE>
 __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 4) k_vjp_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb,
                                                          const float4* __restrict__ erec, int64_t nE, int n_sub,
                                                          float* __restrict__ part) {
-  __shared__ VjpLds<MODE> L;
+  constexpr int J = vjp_j(MODE);
+  __shared__ VjpLds<MODE, J, false> L;
   constexpr int NC = MODE == 0 ? 3 : 10;
   const int t0 = blockIdx.y * tpb;
   const int64_t e_begin = (int64_t)blockIdx.x * n_sub * vjp_chunk(MODE);
   const int sub = (int)min<int64_t>(n_sub, (nE - e_begin + vjp_chunk(MODE) - 1) / vjp_chunk(MODE));
-  vjp_lanes_tile<MODE>(rec, nt, t0, min(nt, t0 + tpb), erec, nE, e_begin, sub, g.two_pi_over_L[0],
-                       g.two_pi_over_L[1], g.two_pi_over_L[2], part + (size_t)blockIdx.x * NC * nt, L);
+  vjp_lanes_tile<MODE, J, false>(rec, nt, t0, min(nt, t0 + tpb), erec, nE, e_begin, sub, g.two_pi_over_L[0],
+                                 g.two_pi_over_L[1], g.two_pi_over_L[2], part + (size_t)blockIdx.x * NC * nt, nullptr,
+                                 L);
+}
+
+// Fused forward and gradient sweep for a given cotangent: one entry chunk of
+// fused_chunk(MODE) entries per block (blockIdx.x) times a range of tpb
+// triangles (blockIdx.y).  Writes the gradient partials part[x][NC][nt] like
+// k_vjp_lanes and the forward partials fpart[y][nE] like k_fwd_lanes.  Same
+// register budgets as the gradient sweep (one entry per lane fewer).
+constexpr int FUSED_WAVES_VOLUME = 4, FUSED_WAVES_SURFACE = 4;
+template <int MODE>
+__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? FUSED_WAVES_VOLUME : FUSED_WAVES_SURFACE)
+    k_fused_lanes(GridC g, const float* __restrict__ rec, int nt, int tpb, const float4* __restrict__ erec,
+                  int64_t nE, float* __restrict__ part, float2* __restrict__ fpart) {
+  constexpr int J = fused_j(MODE);
+  __shared__ VjpLds<MODE, J, true> L;
+  constexpr int NC = MODE == 0 ? 3 : 10;
+  const int t0 = blockIdx.y * tpb;
+  const int64_t e_begin = (int64_t)blockIdx.x * fused_chunk(MODE);
+  vjp_lanes_tile<MODE, J, true>(rec, nt, t0, min(nt, t0 + tpb), erec, nE, e_begin, 1, g.two_pi_over_L[0],
+                                g.two_pi_over_L[1], g.two_pi_over_L[2], part + (size_t)blockIdx.x * NC * nt,
+                                fpart + (size_t)blockIdx.y * nE, L);
 }
 
 // Persistent sweeps over the work items of many independent meshes: one
@@ -1445,11 +1580,11 @@ __device__ __forceinline__ SweepReq uni(const SweepReq& q) {
   u.epc = uni(q.epc);
   u.vsub = uni(q.vsub);
   u.vtpb = uni(q.vtpb);
-  u.pad = 0;
+  u.tile0 = uni(q.tile0);
   u.tpx = uni(q.tpx);
   u.tpy = uni(q.tpy);
   u.tpz = uni(q.tpz);
-  u.pad2 = 0.0f;
+  u.ntr = uni(q.ntr);
   u.kf = uni(q.kf);
   u.rec = uni(q.rec);
   u.fpart = uni(q.fpart);
@@ -1488,8 +1623,9 @@ __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 4)
     k_batch_vjp(const SweepItem* __restrict__ items, int n_items, const SweepReq* __restrict__ reqs,
                 int* __restrict__ counter) {
   constexpr int NC = MODE == 0 ? 3 : 10;
+  constexpr int J = vjp_j(MODE);
   __shared__ int slot;
-  __shared__ VjpLds<MODE> L;
+  __shared__ VjpLds<MODE, J, false> L;
   for (;;) {
     const int it = next_item(counter, &slot);
     if (it >= n_items) return;
@@ -1498,8 +1634,35 @@ __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? 5 : 4)
     const int64_t e_begin = (int64_t)w.c * q.epc;
     const int sub = (int)min<int64_t>(q.vsub, ((int64_t)q.nE - e_begin + vjp_chunk(MODE) - 1) / vjp_chunk(MODE));
     const int t1 = min(q.nt, w.x0 + q.vtpb);
-    vjp_lanes_tile<MODE, MODE == 0>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy, q.tpz,
-                         q.vpart + (size_t)w.c * NC * q.nt, L);
+    vjp_lanes_tile<MODE, J, false, MODE == 0>(q.rec, q.nt, w.x0, t1, q.erec, q.nE, e_begin, sub, q.tpx, q.tpy,
+                                              q.tpz, q.vpart + (size_t)w.c * NC * q.nt, nullptr, L);
+  }
+}
+
+// Persistent fused sweep (forward and gradient) over the tiles of many
+// requests: tile t of request r (t counted from its tile0) is entry chunk
+// t / ntr and triangle range t % ntr, so each request's partials have the
+// layout of k_fused_lanes with its own triangle ranges.  Workgroups take the
+// next tile from a counter; tiles come in increasing order, so a workgroup
+// finds its request by advancing from the previous one.
+template <int MODE>
+__global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? FUSED_WAVES_VOLUME : FUSED_WAVES_SURFACE)
+    k_batch_fused(const SweepReq* __restrict__ reqs, int n_reqs, int n_tiles, int* __restrict__ counter) {
+  constexpr int NC = MODE == 0 ? 3 : 10;
+  constexpr int J = fused_j(MODE);
+  __shared__ int slot;
+  __shared__ VjpLds<MODE, J, true> L;
+  int r = 0;
+  for (;;) {
+    const int tile = next_item(counter, &slot);
+    if (tile >= n_tiles) return;
+    while (r + 1 < n_reqs && tile >= uni(reqs[r + 1].tile0)) ++r;
+    const SweepReq q = uni(reqs[r]);
+    const int local = tile - q.tile0;
+    const int c = local / q.ntr, y = local - c * q.ntr;
+    const int t0 = y * q.vtpb, t1 = min(q.nt, t0 + q.vtpb);
+    vjp_lanes_tile<MODE, J, true>(q.rec, q.nt, t0, t1, q.erec, q.nE, (int64_t)c * fused_chunk(MODE), 1, q.tpx, q.tpy,
+                                  q.tpz, q.vpart + (size_t)c * NC * q.nt, q.fpart + (size_t)y * q.nE, L);
   }
 }
 
@@ -1730,21 +1893,34 @@ hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hip
   return hipGetLastError();
 }
 
-hipError_t launch_batch_sweep(const SweepItem* items, const int* group_end, const SweepReq* reqs, int* counters,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(counters), (int64_t)4);
+hipError_t launch_batch_sweep(const SweepItem* items, const int* group_end, const SweepReq* reqs,
+                              const SweepReq* const* fused_reqs, const int* n_fused_reqs, const int* n_fused_tiles,
+                              int* counters, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(counters),
+                     (int64_t)BATCH_GROUPS);
+  const dim3 threads(SWEEP_T);
   int begin = 0;
   for (int grp = 0; grp < 4; ++grp) {
     const int n = group_end[grp] - begin;
     if (n > 0) {
       const SweepItem* it = items + begin;
-      const dim3 blocks((unsigned)std::min(n, grp < 2 ? 2048 : 1280)), threads(SWEEP_T);
+      // one resident round of workgroups (4 waves each) at the kernel's occupancy
+      const dim3 blocks((unsigned)std::min(n, grp < 2 ? 2048 : 1280));
       if (grp == 0) hipLaunchKernelGGL(k_batch_fwd<0>, blocks, threads, 0, s, it, n, reqs, counters);
       if (grp == 1) hipLaunchKernelGGL(k_batch_fwd<1>, blocks, threads, 0, s, it, n, reqs, counters + 1);
       if (grp == 2) hipLaunchKernelGGL(k_batch_vjp<0>, blocks, threads, 0, s, it, n, reqs, counters + 2);
       if (grp == 3) hipLaunchKernelGGL(k_batch_vjp<1>, blocks, threads, 0, s, it, n, reqs, counters + 3);
     }
     begin = group_end[grp];
+  }
+  for (int m = 0; m < 2; ++m) {
+    const int n = n_fused_tiles[m];
+    if (n <= 0 || n_fused_reqs[m] <= 0) continue;
+    const dim3 blocks((unsigned)std::min(n, 1024));   // 4 waves per SIMD: 4 workgroups per CU
+    if (m == 0)
+      hipLaunchKernelGGL(k_batch_fused<0>, blocks, threads, 0, s, fused_reqs[0], n_fused_reqs[0], n, counters + 4);
+    else
+      hipLaunchKernelGGL(k_batch_fused<1>, blocks, threads, 0, s, fused_reqs[1], n_fused_reqs[1], n, counters + 5);
   }
   return hipGetLastError();
 }
@@ -1762,6 +1938,19 @@ hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int 
   else
     hipLaunchKernelGGL(k_vjp_lanes<1>, grid, dim3(SWEEP_T), 0, s, g, tri_rec, nt, tris_per_block, erec, nE,
                        chunks_per_block, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,
+                              const float4* erec, int64_t nE, float* part, float2* fpart, hipStream_t s) {
+  if (tris_per_block < 1 || nE < 1 || nt < 1) return hipErrorInvalidValue;
+  const dim3 grid(blocks_for(nE, fused_chunk(mode)), blocks_for(nt, tris_per_block));
+  if (mode == 0)
+    hipLaunchKernelGGL(k_fused_lanes<0>, grid, dim3(SWEEP_T), 0, s, g, tri_rec, nt, tris_per_block, erec, nE, part,
+                       fpart);
+  else
+    hipLaunchKernelGGL(k_fused_lanes<1>, grid, dim3(SWEEP_T), 0, s, g, tri_rec, nt, tris_per_block, erec, nE, part,
+                       fpart);
   return hipGetLastError();
 }
 

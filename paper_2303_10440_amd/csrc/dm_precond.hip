@@ -20,6 +20,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cmath>
+#include <utility>
+
 #include "dm_internal.h"
 
 namespace dm {
@@ -112,118 +116,78 @@ __device__ __forceinline__ void lap_row(int i, const int32_t* __restrict__ off, 
   }
 }
 
-template <bool TABLE>
-__device__ int cg_solve(int nv, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr,
-                        const int32_t* __restrict__ tab, const float* __restrict__ dinv_v, float lam, const float* b,
-                        float* x,
-                        float* __restrict__ r, float* __restrict__ p, float* __restrict__ q, int max_iter, float tol,
-                        float* res, CgLds& L) {
-  double bz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // b.b, then r.z, per component
-  for (int i = threadIdx.x; i < nv; i += CG_T) {
-    const float dinv = dinv_v[i];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float bi = b[3 * i + c];
-      r[3 * i + c] = bi;
-      p[3 * i + c] = bi * dinv;
-      bz[c] += (double)bi * bi;
-      bz[3 + c] += (double)bi * (bi * dinv);
-    }
-  }
-  // x = 0 after the reads of b above (x may be the same array as b)
-  __syncthreads();
-  for (int i = threadIdx.x; i < nv; i += CG_T)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[3 * i + c] = 0.0f;
-  block_sum<6>(bz, L);
-  const double bb[3] = {bz[0], bz[1], bz[2]};
-  double rz[3] = {bz[3], bz[4], bz[5]};
-  double rr[3] = {bb[0], bb[1], bb[2]};
-  const double tol2 = (double)tol * tol;
-  int it = 0;
-  for (; it < max_iter; ++it) {
-    if (rr[0] <= tol2 * bb[0] && rr[1] <= tol2 * bb[1] && rr[2] <= tol2 * bb[2]) break;
-    // q = (I + lam L) p, and p.q
-    double pq[3] = {0.0, 0.0, 0.0};
-#pragma unroll 2
-    for (int i = threadIdx.x; i < nv; i += CG_T) {
-      float s[3];
-      int deg;
-      lap_row<TABLE>(i, off, nbr, tab, p, s, deg);
-      const float d = fmaf(lam, (float)deg, 1.0f);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float pi = p[3 * i + c];
-        const float qi = fmaf(d, pi, -lam * s[c]);
-        q[3 * i + c] = qi;
-        pq[c] += (double)pi * qi;
-      }
-    }
-    block_sum<3>(pq, L);
-    float alpha[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) alpha[c] = pq[c] > 0.0 ? (float)(rz[c] / pq[c]) : 0.0f;
-    // x += alpha p, r -= alpha q; r.r and r.z with z = r / d
-    double rn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // r.r, then r.z
-    for (int i = threadIdx.x; i < nv; i += CG_T) {
-      const float dinv = dinv_v[i];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        x[3 * i + c] = fmaf(alpha[c], p[3 * i + c], x[3 * i + c]);
-        const float ri = fmaf(-alpha[c], q[3 * i + c], r[3 * i + c]);
-        r[3 * i + c] = ri;
-        rn[c] += (double)ri * ri;
-        rn[3 + c] += (double)ri * (ri * dinv);
-      }
-    }
-    block_sum<6>(rn, L);
-    float beta[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      beta[c] = rz[c] > 0.0 ? (float)(rn[3 + c] / rz[c]) : 0.0f;
-      rz[c] = rn[3 + c];
-      rr[c] = rn[c];
-    }
-    // p = z + beta p
-    for (int i = threadIdx.x; i < nv; i += CG_T) {
-      const float dinv = dinv_v[i];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) p[3 * i + c] = fmaf(beta[c], p[3 * i + c], r[3 * i + c] * dinv);
-    }
-    __syncthreads();
-  }
-  double worst = 0.0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    if (bb[c] > 0.0) worst = fmax(worst, sqrt(rr[c] / bb[c]));
-  *res = (float)worst;
-  return it;
+// Chebyshev iteration for (I + lam L) x = b on meshes the resident CG does
+// not hold: the spectrum of I + lam L lies in [1, 1 + lam mu] (L = D - A has
+// the eigenvalue 0 on constant vectors, and its largest eigenvalue is at most
+// mu = the largest d_i + d_j over the mesh edges, the bound of Anderson and
+// Morley), so with theta and delta the centre and half-width of that interval
+// and sigma = theta / delta the three-term recurrence
+//   x_{k+1} = x_k + d_k,   r_{k+1} = r_k - A d_k,
+//   rho_{k+1} = 1 / (2 sigma - rho_k),
+//   d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) r_{k+1},
+// started from x_0 = 0, r_0 = b, rho_0 = 1 / sigma, d_0 = b / theta, reduces
+// every column's residual by at least 2 rho^k after k steps, rho =
+// (sqrt(kappa) - 1) / (sqrt(kappa) + 1), kappa = 1 + lam mu.  It needs no inner
+// products: each step is one launch over the vertices (the neighbour sum of
+// d from the previous step is the only exchange), with its two coefficients
+// from the host.
+
+// x = 0, r = b, d = b / theta.  x may be the array b (b is read first).
+__global__ void k_cheb_init(int nv, const float* b, float* x, float* __restrict__ r, float* __restrict__ d,
+                            float inv_theta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * nv) return;
+  const float bi = b[i];
+  r[i] = bi;
+  d[i] = bi * inv_theta;
+  x[i] = 0.0f;
 }
 
+// One step: with q = (I + lam L) d at vertex i, x += d, r -= q and, unless it
+// is the last step, d_next = c1 d + c2 r.  d is read at the neighbours, so the
+// next direction goes to another array.
 template <bool TABLE>
-__global__ void __launch_bounds__(CG_T) k_laplace_smooth(int nv, const int32_t* __restrict__ off,
-                                                          const int32_t* __restrict__ nbr,
-                                                          const int32_t* __restrict__ tab, float lam,
-                                                          const float* g, float* out, float* __restrict__ ws,
-                                                          int max_iter, float tol, float* __restrict__ info) {
+__global__ void k_cheb_step(int nv, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                            const int32_t* __restrict__ tab, float lam, const float* __restrict__ d,
+                            float* __restrict__ x, float* __restrict__ r, float* __restrict__ d_next, float c1,
+                            float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  float s[3];
+  int deg;
+  lap_row<TABLE>(i, off, nbr, tab, d, s, deg);
+  const float dg = fmaf(lam, (float)deg, 1.0f);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float di = d[3 * i + c];
+    const float q = fmaf(dg, di, -lam * s[c]);
+    x[3 * i + c] += di;
+    const float ri = r[3 * i + c] - q;
+    r[3 * i + c] = ri;
+    if (d_next != nullptr) d_next[3 * i + c] = fmaf(c1, di, c2 * ri);
+  }
+}
+
+// info[0], info[1] = steps, worst relative residual of the three columns
+// (||r|| / ||b|| in float64, summed in a fixed order by one workgroup).
+__global__ void __launch_bounds__(CG_T) k_cheb_residual(int nv, const float* __restrict__ r,
+                                                        const float* __restrict__ b, float steps,
+                                                        float* __restrict__ info) {
   __shared__ CgLds L;
-  const size_t n3 = (size_t)3 * nv;
-  float* y = ws;
-  float* r = ws + n3;
-  float* p = ws + 2 * n3;
-  float* q = ws + 3 * n3;
-  float* dinv = ws + 4 * n3;   // 1 / diag(I + lam L)
-  for (int i = threadIdx.x; i < nv; i += CG_T) dinv[i] = 1.0f / fmaf(lam, (float)(off[i + 1] - off[i]), 1.0f);
-  __syncthreads();
-  float res1 = 0.0f, res2 = 0.0f;
-  const int it1 = cg_solve<TABLE>(nv, off, nbr, tab, dinv, lam, g, y, r, p, q, max_iter, tol, &res1, L);
-  __syncthreads();
-  const int it2 = cg_solve<TABLE>(nv, off, nbr, tab, dinv, lam, y, out, r, p, q, max_iter, tol, &res2, L);
-  if (info != nullptr && threadIdx.x == 0) {
-    info[0] = (float)it1;
-    info[1] = res1;
-    info[2] = (float)it2;
-    info[3] = res2;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nv; i += CG_T)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[c] += (double)r[3 * i + c] * r[3 * i + c];
+      v[3 + c] += (double)b[3 * i + c] * b[3 * i + c];
+    }
+  block_sum<6>(v, L);
+  if (threadIdx.x == 0) {
+    double worst = 0.0;
+    for (int c = 0; c < 3; ++c)
+      if (v[3 + c] > 0.0) worst = fmax(worst, sqrt(v[c] / v[3 + c]));
+    info[0] = steps;
+    info[1] = (float)worst;
   }
 }
 
@@ -369,8 +333,48 @@ __global__ void __launch_bounds__(CG_T) k_laplace_smooth_res(int nv, const int32
 
 size_t laplace_smooth_workspace(int nv) { return sizeof(float) * 13 * (size_t)nv; }
 
+int chebyshev_steps(float lam, int mu, float tol, int max_iter) {
+  const double kappa = 1.0 + (double)lam * (double)mu;
+  if (!(kappa > 1.0)) return 0;
+  const double sk = std::sqrt(kappa), rho = (sk - 1.0) / (sk + 1.0);
+  const double k = std::ceil(std::log(2.0 / (double)tol) / -std::log(rho));
+  return (int)std::max(1.0, std::min((double)max_iter, k));
+}
+
+namespace {
+
+// One Chebyshev solve (see k_cheb_step): b, x [nv][3]; r, d0, d1 work arrays.
+hipError_t cheb_solve(int nv, const int32_t* adj_off, const int32_t* adj_nbr, const int32_t* adj_tab, float lam,
+                      int mu, int steps, const float* b, float* x, float* r, float* d0, float* d1, float* info,
+                      hipStream_t s) {
+  const double lo = 1.0, hi = 1.0 + (double)lam * (double)mu;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  const unsigned b3 = (unsigned)((3 * (int64_t)nv + 255) / 256), b1 = (unsigned)((nv + 255) / 256);
+  hipLaunchKernelGGL(k_cheb_init, dim3(b3), dim3(256), 0, s, nv, b, x, r, d0, (float)(1.0 / theta));
+  double rho = 1.0 / sigma;
+  float* d = d0;
+  float* dn = d1;
+  for (int k = 0; k < steps; ++k) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    const bool last = k + 1 == steps;
+    const float c1 = (float)(rho1 * rho), c2 = (float)(2.0 * rho1 / delta);
+    if (adj_tab != nullptr)
+      hipLaunchKernelGGL(k_cheb_step<true>, dim3(b1), dim3(256), 0, s, nv, adj_off, adj_nbr, adj_tab, lam, d, x, r,
+                         last ? nullptr : dn, c1, c2);
+    else
+      hipLaunchKernelGGL(k_cheb_step<false>, dim3(b1), dim3(256), 0, s, nv, adj_off, adj_nbr, adj_tab, lam, d, x, r,
+                         last ? nullptr : dn, c1, c2);
+    rho = rho1;
+    std::swap(d, dn);
+  }
+  if (info != nullptr) hipLaunchKernelGGL(k_cheb_residual, dim3(1), dim3(CG_T), 0, s, nv, r, b, (float)steps, info);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* adj_nbr, const int32_t* adj_tab,
-                                 float lam, const float* g, float* out, float* ws, int max_iter, float tol,
+                                 int mu, float lam, const float* g, float* out, float* ws, int max_iter, float tol,
                                  float* info, hipStream_t s) {
   if (adj_tab != nullptr && nv <= CG_T * CG_VPT_MAX) {
     const int vpt = (nv + CG_T - 1) / CG_T;
@@ -383,13 +387,29 @@ hipError_t launch_laplace_smooth(int nv, const int32_t* adj_off, const int32_t* 
     else
       hipLaunchKernelGGL(k_laplace_smooth_res<3>, dim3(1), dim3(CG_T), 0, s, nv, adj_tab, lam, g, out, max_iter, tol,
                          info);
-  } else if (adj_tab != nullptr)
-    hipLaunchKernelGGL(k_laplace_smooth<true>, dim3(1), dim3(CG_T), 0, s, nv, adj_off, adj_nbr, adj_tab, lam, g, out,
-                       ws, max_iter, tol, info);
-  else
-    hipLaunchKernelGGL(k_laplace_smooth<false>, dim3(1), dim3(CG_T), 0, s, nv, adj_off, adj_nbr, adj_tab, lam, g,
-                       out, ws, max_iter, tol, info);
-  return hipGetLastError();
+    return hipGetLastError();
+  }
+  const int steps = chebyshev_steps(lam, mu, tol, max_iter);
+  const size_t n3 = (size_t)3 * nv;
+  float* y = ws;
+  float* r = ws + n3;
+  float* d0 = ws + 2 * n3;
+  float* d1 = ws + 3 * n3;
+  if (steps == 0) {   // I + lam L = I (lam = 0 or no edges): out = g
+    if (out != g) {
+      const hipError_t e = hipMemcpyAsync(out, g, n3 * sizeof(float), hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+    }
+    if (info != nullptr) {
+      hipLaunchKernelGGL(k_cheb_residual, dim3(1), dim3(CG_T), 0, s, 0, y, g, 0.0f, info);
+      hipLaunchKernelGGL(k_cheb_residual, dim3(1), dim3(CG_T), 0, s, 0, y, g, 0.0f, info + 2);
+    }
+    return hipGetLastError();
+  }
+  const hipError_t e = cheb_solve(nv, adj_off, adj_nbr, adj_tab, lam, mu, steps, g, y, r, d0, d1, info, s);
+  if (e != hipSuccess) return e;
+  return cheb_solve(nv, adj_off, adj_nbr, adj_tab, lam, mu, steps, y, out, r, d0, d1,
+                    info != nullptr ? info + 2 : nullptr, s);
 }
 
 }  // namespace dm

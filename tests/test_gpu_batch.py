@@ -132,10 +132,12 @@ def test_batch_rejects_whole_batch_and_writes_nothing(dm, handle):
         assert bool((img == 7.0).all()) and bool((dv == 7.0).all())
 
 
-def test_large_request_in_a_batch_runs_its_own_sweeps(dm, handle):
-    """A request of 2.8e9 pairs (the single cell) is large enough to run its
-    own sweep launches inside a batch: its outputs are bitwise those of the
-    single call, while a small request shares the persistent launch."""
+def test_large_request_in_the_shared_launch(dm, handle):
+    """A request of 2.8e9 pairs (the single cell) in the shared persistent
+    launch with a small one: its outputs agree with dm_render_vjp to float32
+    rounding (the batch cuts it into larger tiles) and are bitwise those of a
+    batch of itself alone; the small request's are bitwise those of a batch of
+    itself alone."""
     import torch
     big = configs.cfg3()
     small = configs.cfg1()
@@ -143,26 +145,33 @@ def test_large_request_in_a_batch_runs_its_own_sweeps(dm, handle):
     ts = handle.topology(small.F, n_verts=len(small.V))
     Gb = dev(np.random.default_rng(21).standard_normal(big.grid.n).astype(np.float32))
     Gs = dev(np.random.default_rng(22).standard_normal(small.grid.n).astype(np.float32))
-    single = dm.render_vjp(handle, dev(big.V), tb, big.sigma, big.grid, Gb, want_image=True)
-    out = dm.batch_run(handle, [(dev(small.V), ts, small.sigma, small.grid, Gs),
-                                (dev(big.V), tb, big.sigma, big.grid, Gb)])
-    alone = dm.batch_run(handle, [(dev(small.V), ts, small.sigma, small.grid, Gs)])
+    rb = (dev(big.V), tb, big.sigma, big.grid, Gb)
+    rs = (dev(small.V), ts, small.sigma, small.grid, Gs)
+    single = dm.render_vjp(handle, *rb, want_image=True)
+    out = dm.batch_run(handle, [rs, rb])
+    alone_s = dm.batch_run(handle, [rs])
+    alone_b = dm.batch_run(handle, [rb])
     torch.cuda.synchronize()
     img, dv, ds = out[1]
-    say("large request in batch: image equal", torch.equal(img, single[2]), "dV equal", torch.equal(dv, single[0]))
-    assert torch.equal(img, single[2]) and torch.equal(dv, single[0]) and torch.equal(ds, single[1])
-    for a, b in zip(out[0], alone[0]):
+    e_img = float((img - single[2]).norm() / single[2].norm())
+    e_dv = float((dv - single[0]).norm() / single[0].norm())
+    e_ds = float((ds - single[1]).norm() / single[1].norm())
+    say("large request in batch vs single call: image", e_img, "dV", e_dv, "dSigma", e_ds)
+    assert e_img < 1e-6 and e_dv < 1e-5 and e_ds < 1e-5
+    for a, b in zip(out[1], alone_b[0]):
+        assert torch.equal(a, b)
+    for a, b in zip(out[0], alone_s[0]):
         assert torch.equal(a, b)
 
 
-def test_several_large_requests_alternate_streams(dm, handle):
+def test_several_large_requests_in_one_launch(dm, handle):
     """Three large requests (the single cell in both density modes, and the
-    volume cell with another PSF) and two small ones in one batch: the large
-    ones run their own sweeps, alternating between the caller's stream and
-    the handle's second stream, and their outputs are bitwise the single
-    call's; the small ones share the persistent launch and match a batch of
-    themselves alone bitwise.  The batch is complete when the caller's stream
-    is (read right after it, with no device-wide synchronisation)."""
+    volume cell with another PSF) and two small ones in one batch, all in the
+    shared persistent launches (one per density): every request's outputs are
+    bitwise those of a batch of itself alone, and the large ones agree with
+    dm_render_vjp to float32 rounding.  The batch is complete when the
+    caller's stream is (read right after it, with no device-wide
+    synchronisation)."""
     import torch
     big = configs.cfg3(VOLUME)
     bigs = configs.cfg3(SURFACE)
@@ -181,18 +190,49 @@ def test_several_large_requests_alternate_streams(dm, handle):
             (dev(small.V) * 1.01, ts, small.sigma, small.grid, Gs),
             (dev(big.V), tb, sig2, big.grid, Gb)]
     large = {0, 2, 4}
-    refs = []
-    for i, r in enumerate(reqs):
-        if i in large:
-            dv, ds, img = dm.render_vjp(handle, *r, want_image=True)
-            refs.append((img, dv, ds))
-        else:
-            refs.append(dm.batch_run(handle, [r])[0])
+    refs = [dm.batch_run(handle, [r])[0] for r in reqs]
+    singles = {i: dm.render_vjp(handle, *reqs[i], want_image=True) for i in large}
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     out = dm.batch_run(handle, reqs)
     s.synchronize()
     for i, (o, ref) in enumerate(zip(out, refs)):
         eq = all(torch.equal(a, b) for a, b in zip(o, ref))
-        say(f"request {i} ({'own sweeps' if i in large else 'shared launch'}): outputs equal: {eq}")
+        say(f"request {i} ({'large' if i in large else 'small'}): outputs equal to the request alone: {eq}")
         assert eq
+        if i in large:
+            dv, ds, img = singles[i]
+            assert float((o[0] - img).norm() / img.norm()) < 1e-6
+            assert float((o[1] - dv).norm() / dv.norm()) < 1e-5
+
+
+def test_cfg4_sized_request_in_the_shared_launch_vs_oracle(dm, handle, ref):
+    """The largest cell of the 64-cell batched workload (by pairs), run in the
+    shared persistent launch between two other cells of that workload: its
+    vertex gradient at 12 sampled vertices against the FP64 oracle evaluated
+    on the triangles around them (each triangle adds its own terms to its
+    vertices' gradients, so those triangles fix them exactly), and its image
+    against the single call to rounding."""
+    import torch
+    cases = configs.cfg4()
+    sizes = [len(c.F) * dm.band_size(handle, f32_grid(c.grid), f32_sigma(c.sigma)) for c in cases]
+    order = np.argsort(sizes)
+    ib, i1, i2 = int(order[-1]), int(order[0]), int(order[len(order) // 2])
+    say("cfg4 largest cell", cases[ib].name, "triangles", len(cases[ib].F), "pairs", sizes[ib])
+    reqs = _requests(dm, handle, [cases[i1], cases[ib], cases[i2]], seed=7)
+    out = dm.batch_run(handle, reqs)
+    V, topo, S, g, G = reqs[1]
+    dv1, ds1, img1 = dm.render_vjp(handle, V, topo, S, g, G, want_image=True)
+    torch.cuda.synchronize()
+    img, dv, ds = out[1]
+    assert rel_l2(img.cpu().numpy(), img1.cpu().numpy()) < 1e-6
+    c = cases[ib]
+    Vd = c.V.astype(np.float64)
+    bmask, xb, hb, Gb, W = ref.vjp_band(g, S, G.cpu().numpy().astype(np.float64))
+    vs = np.random.default_rng(23).choice(len(Vd), 12, replace=False)
+    tris = np.nonzero(np.isin(c.F, vs).any(axis=1))[0]
+    Vr = Vd - np.asarray(g.origin, dtype=np.float64)
+    want = ref.mesh_ft_vjp_raw(Vr, c.F[tris], xb, W, VOLUME)[vs]
+    err = rel_l2(dv.cpu().numpy().astype(np.float64)[vs], want)
+    say("cfg4 largest cell in the shared launch: dV rel l2 at 12 vertices", err)
+    assert err < 1e-4

@@ -59,9 +59,12 @@ def test_aberrated_otf_image_and_gradient(dm, handle, ref, mode, gi):
                                  want_image=True)
     dvw = ref.render_otf_vjp(V64, c.F, g, otf.astype(np.complex128), G.astype(np.float64))
     e_img, e_dv = rel_l2(img, want), rel_l2(dv.cpu().numpy(), dvw)
-    say("  image", e_img, "dV", e_dv)
-    assert e_img < 1e-5 and e_dv < 1e-4
-    assert np.array_equal(img, img2.cpu().numpy())
+    e_img2 = rel_l2(img2.cpu().numpy(), want)
+    say("  image", e_img, "dV", e_dv, "image of the gradient call", e_img2)
+    assert e_img < 1e-5 and e_dv < 1e-4 and e_img2 < 1e-5
+    # the gradient call computes its image in the fused sweep: the same sums in
+    # another float32 order
+    assert rel_l2(img2.cpu().numpy(), img) < 1e-6
 
 
 def test_tabulated_gaussian_equals_the_gaussian_path(dm, handle, ref):

@@ -404,3 +404,32 @@ def test_error_paths(dm, handle):
     with pytest.raises(dm.DeltamicError) as e:
         dm.render(handle, dev(V[:-1]), topo, S, g)
     assert e.value.status == -1
+
+
+def test_band_cache_stays_bounded_over_many_psfs(dm):
+    """A handle that renders with a new covariance every call (a PSF fit, a
+    server whose requests carry their own PSFs) keeps a bounded band cache:
+    at most 32 bands (least recently used evicted), so its device memory stops
+    growing; a band evicted and needed again is rebuilt identically."""
+    import torch
+    h = dm.Handle(0)
+    c = configs.cfg1()
+    g = f32_grid(c.grid)
+    topo = h.topology(c.F, n_verts=len(c.V))
+    V = dev(c.V)
+    sig = lambda i: (1.0 + 0.01 * i, 1.0 + 0.01 * i, 2.5, 0.0, 0.0, 0.0)
+    first = dm.render(h, V, topo, sig(0), g)
+    mem, sizes = [], []
+    for i in range(50):
+        dm.render(h, V, topo, sig(i), g)
+        torch.cuda.synchronize()
+        mem.append(h.memory_in_use())
+        sizes.append(dm.band_size(h, g, sig(i)))
+    n_pos = g.n[0] * g.n[1] * (g.n[2] // 2 + 1)
+    band_bytes = 24 * max(sizes) + 4 * n_pos + 4096
+    say("band cache: memory after 1/32/50 PSFs", mem[0], mem[31], mem[49], "band <=", band_bytes)
+    assert mem[49] <= mem[0] + 32 * band_bytes
+    assert mem[49] <= mem[31] + 2 * band_bytes
+    again = dm.render(h, V, topo, sig(0), g)   # its band was evicted and is rebuilt
+    torch.cuda.synchronize()
+    assert torch.equal(first, again)

@@ -160,8 +160,10 @@ def test_served_large_requests_on_two_streams(dm):
     """Three requests large enough to run their own sweeps (the single cell,
     both density modes, and the volume cell with a wider PSF) submitted with
     small ones: in a batch the large ones alternate between the batch's
-    stream and the handle's second stream, each handed out at its own
-    completion.  Every result equals the same request run alone."""
+    stream and the slot's second stream, each handed out at its own
+    completion.  Every result equals the same request run alone: the large
+    ones bitwise dm_render_vjp (they run its sweep plan), the small ones
+    bitwise a batch of themselves alone."""
     import torch
     say("serve large requests on two streams")
     big = configs.cfg3(VOLUME)
@@ -188,7 +190,10 @@ def test_served_large_requests_on_two_streams(dm):
             g, G = b[0], b[1]
             topo = h.topology(c.F, n_verts=len(c.V))
             V = torch.tensor(c.V, device="cuda:0")
-            img, dv, ds = dm.batch_run(h, [(V, topo, f32_sigma(sig), g, G)])[0]
+            if c is big or c is bigs:
+                dv, ds, img = dm.render_vjp(h, V, topo, f32_sigma(sig), g, G, want_image=True)
+            else:
+                img, dv, ds = dm.batch_run(h, [(V, topo, f32_sigma(sig), g, G)])[0]
             eq = bool((img == b[2]).all()) and bool((dv == b[3]).all()) and bool((ds == b[4]).all())
             say(f"request {i}: served equals alone: {eq}")
             assert eq
