@@ -473,7 +473,9 @@ def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_in
                        "forward + gradient each",
            "rate": rate, "offered_pairs_per_s": rate * float(np.mean([pairs_of[int(i)] for i in idx]))}
     out["batched"] = run(max_batch, max_inflight)
+    print(f"serve {rate:g}/s batched: {out['batched']}", file=sys.stderr, flush=True)
     out["plain"] = run(1, 1)
+    print(f"serve {rate:g}/s plain: {out['plain']}", file=sys.stderr, flush=True)
     out["throughput_gain"] = out["batched"]["throughput_rps"] / out["plain"]["throughput_rps"]
     return out
 
@@ -499,7 +501,8 @@ def main() -> int:
                     help="add the staggered shape / PSF fitting steps on the single-cell workload")
     ap.add_argument("--serve", type=float, nargs="*", default=None,
                     help="add the serving comparison at these arrival rates (req/s)")
-    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--serve-count", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -647,7 +650,8 @@ def main() -> int:
     if args.otf:
         out["otf"] = bench_otf(dm, case)
     if args.serve is not None:
-        out["serving"] = [bench_serve(dm, r, args.serve_count, 20, 16, 2) for r in (args.serve or [200.0])]
+        out["serving"] = [bench_serve(dm, r, args.serve_count, args.serve_warmup, 16, 2)
+                          for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, g, sigma, mode, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]

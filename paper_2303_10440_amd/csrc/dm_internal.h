@@ -43,9 +43,8 @@ struct BandDev {
 // Triangle record for the sweeps: 16 floats (one 64-byte scalar load), for
 // the triangle (v1, v2, v3) in strip order (v3 is the vertex it adds).
 //  [0..2] u3_hi, [3..5] u3_lo : (v3 - c)/L split into a 12-bit grid part and rest
-//  [6..8] e2 = (v2 - v1)/L,  [9..11] e3 = (v3 - v1)/L
-//  [12..14] VOLUME: n_T / (4 pi^2 L), n_T the outward (v2-v1)x(v3-v1) (the 1 / (4 pi^2)
-//           of the closed form folded in);  SURFACE: [12] = 2 A_T
+//  [6..8] e2 = 2 pi (v2 - v1)/L,  [9..11] e3 = 2 pi (v3 - v1)/L  (k.e: relative phases in radians)
+//  [12..14] VOLUME: n_T / L, n_T the outward (v2-v1)x(v3-v1);  SURFACE: [12] = 2 A_T
 //  [15] 1 for the first triangle of a strip, else 0
 constexpr int TRI_REC = 16;
 constexpr float PHASE_GRID = 4096.0f;   // 2^12

@@ -14,12 +14,14 @@
 //     (z_hi - z_lo) with each DD2 in its sinc form, and the repeated-node
 //     DD4 from the same recurrence with the second phi-function
 //     phi2(z) = (e^z - 1 - z)/z^2.
-// Phases are carried in revolutions (k . u with integer k and u = x / L), so
-// the large part of every phase is reduced exactly before the hardware
-// sine and cosine (v_sin_f32 / v_cos_f32 take revolutions).
+// Vertex phases are carried in revolutions (k . u with integer k and u =
+// x / L), so the large part of every phase is reduced exactly before the
+// hardware sine and cosine (v_sin_f32 / v_cos_f32 take revolutions); the
+// closed forms take the phases of two vertices relative to the third in
+// radians, small numbers computed from the edges.
 //
 // Work layout: both sweeps put band frequencies on lanes and stream triangle
-// records as wave-uniform values through the scalar data cache.  The gradient
+// records as wave-uniform values.  The gradient
 // sweep evaluates most pairs in the closed Lagrange form and queues the pairs
 // with nearly coincident nodes in LDS for the stable scheme above, so the
 // stable branch runs on full waves.  Every reduction is a fixed-order sum (no
@@ -42,11 +44,13 @@ constexpr double TWO_PI_D = 6.283185307179586476925286766559;
 constexpr float SERIES_REV = 0.15915494309189535f;   // 1 / (2 pi)
 constexpr float INV_TWO_PI_F = 0.15915494309189535f;
 // Closed (Lagrange) form of the gradient pair when every node gap is at least
-// LAG_GAP revolutions and the spread at least SERIES_REV; other pairs go to
+// 0.01 revolutions and the spread at least one radian; other pairs go to
 // vjp_pair_series / vjp_pair_sorted.  Its float32 rounding grows like 1 / (2 pi gap)^2; at this gap the
 // vertex gradients stay within about 1e-5 relative of the float64 result, an
-// order of magnitude inside the gradient tolerance.
-constexpr float LAG_GAP = 0.01f;
+// order of magnitude inside the gradient tolerance.  The main loops compare
+// relative phases in radians.
+constexpr float LAG_GAP_RAD = 0.06283185307179587f;   // 0.01 rev
+constexpr float SERIES_RAD = 1.0f;
 
 // e^{-2 pi i r} for r in revolutions, r already in [-1/2, 1/2].
 __device__ __forceinline__ void cis_neg(float r, float& c, float& s_neg) {
@@ -93,25 +97,23 @@ __device__ __forceinline__ float vertex3_wphase(float kx, float ky, float kz, co
   const float lo = fmaf(kz, r[5], fmaf(ky, r[4], fmaf(kx, r[3], -w)));
   return __builtin_amdgcn_fractf(__builtin_amdgcn_fractf(-th) - lo);
 }
+// Phases of vertices 2 and 3 relative to vertex 1 in radians (the record
+// holds the edges times 2 pi / L).
 __device__ __forceinline__ void rel_phases(float kx, float ky, float kz, const float* r, float& d2, float& d3) {
   d2 = fmaf(kz, r[8], fmaf(ky, r[7], kx * r[6]));
   d3 = fmaf(kz, r[11], fmaf(ky, r[10], kx * r[9]));
 }
-// Phase of vertex 1 and the two relative phases.
+// The same in revolutions.
+__device__ __forceinline__ void rel_phases_rev(float kx, float ky, float kz, const float* r, float& d2, float& d3) {
+  rel_phases(kx, ky, kz, r, d2, d3);
+  d2 *= INV_TWO_PI_F;
+  d3 *= INV_TWO_PI_F;
+}
+// Phase of vertex 1 and the two relative phases (revolutions).
 __device__ __forceinline__ void tri_phases(float kx, float ky, float kz, const float* r, float& t1, float& d2,
                                            float& d3) {
-  rel_phases(kx, ky, kz, r, d2, d3);
+  rel_phases_rev(kx, ky, kz, r, d2, d3);
   t1 = vertex3_phase(kx, ky, kz, r) - d3;
-}
-
-// Copy of a wave-uniform value into a VGPR.  On gfx950 FP32 VALU
-// instructions whose operands are all VGPRs (or literals) issue at up to twice
-// the rate of those that read an SGPR, so triangle data used by every pair is
-// moved to VGPRs once per triangle.
-__device__ __forceinline__ float to_vgpr(float x) {
-  float v;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
-  return v;
 }
 
 // Wrap revolutions into [0, 1) for the hardware sine/cosine (v_fract_f32).
@@ -297,45 +299,6 @@ __device__ __forceinline__ void vjp_pair_sorted(float t1, float d2, float d3, fl
   const float v[3] = {0.0f, d2, d3};
 #pragma unroll
   for (int p = 0; p < 3; ++p) z[p] = v[p] == lo ? zl : (v[p] == hi ? zh : zm);
-}
-
-// One gradient pair in closed form (caller checks the gaps, see LAG_GAP).
-// Nodes z_p = -2 pi i t_p with t = (t1, t1 + a, t1 + b); with
-// alpha = 1/(2 pi a), beta = 1/(2 pi b), gamma = 1/(2 pi (b - a)) the divided
-// difference is the Lagrange sum T0 + T1 + T2,
-//   T0 = -alpha beta E0,  T1 = alpha gamma E1,  T2 = -beta gamma E2   (E_p = e^{z_p}),
-// and its derivatives in the nodes (the repeated-node DD4 of Eq. 10) are
-//   DD4_0 = T0 + i[(alpha+beta) T0 + alpha T1 + beta T2]
-//   DD4_1 = T1 + i[(gamma-alpha) T1 - alpha T0 + gamma T2]
-//   DD4_2 = T2 - i[(beta+gamma) T2 + beta T0 + gamma T1].
-// The adjoint weight enters through its modulus and phase, W E_p =
-// |W| e^{-2 pi i (t_p - phi_W)}, so no complex product is formed.
-//   VOLUME:  z[p] = Re(W DD4_p)          SURFACE: wf = Re(W f), z[p] = Im(W DD4_p)
-template <int MODE>
-__device__ __forceinline__ void lag_pair(float t1, float a, float b, float amp, float phw, float& wf, float z[3]) {
-  const float r0 = t1 - phw;
-  const float q0 = wrap(r0), q1 = wrap(r0 + a), q2 = wrap(r0 + b);
-  const float C0 = __builtin_amdgcn_cosf(q0), S0 = -__builtin_amdgcn_sinf(q0);
-  const float C1 = __builtin_amdgcn_cosf(q1), S1 = -__builtin_amdgcn_sinf(q1);
-  const float C2 = __builtin_amdgcn_cosf(q2), S2 = -__builtin_amdgcn_sinf(q2);
-  const float c = b - a;
-  const float ab = a * b;
-  const float rD = __builtin_amdgcn_rcpf(ab * c) * INV_TWO_PI_F;   // 1 / (2 pi a b c)
-  const float al = b * c * rD, be = a * c * rD, ga = ab * rD;
-  const float alw = amp * al;
-  const float k0 = -alw * be, k1 = alw * ga, k2 = -amp * (be * ga);
-  const float R0 = k0 * C0, I0 = k0 * S0, R1 = k1 * C1, I1 = k1 * S1, R2 = k2 * C2, I2 = k2 * S2;
-  const float s01 = al + be, s21 = ga - al, s12 = be + ga;
-  if (MODE == 0) {
-    z[0] = fmaf(-s01, I0, fmaf(-al, I1, fmaf(-be, I2, R0)));
-    z[1] = fmaf(-s21, I1, fmaf(al, I0, fmaf(-ga, I2, R1)));
-    z[2] = fmaf(s12, I2, fmaf(be, I0, fmaf(ga, I1, R2)));
-  } else {
-    wf = R0 + R1 + R2;
-    z[0] = fmaf(s01, R0, fmaf(al, R1, fmaf(be, R2, I0)));
-    z[1] = fmaf(s21, R1, fmaf(-al, R0, fmaf(ga, R2, I1)));
-    z[2] = fmaf(-s12, R2, fmaf(-be, R0, fmaf(-ga, R1, I2)));
-  }
 }
 
 // ------------------------------------------------------------- the band
@@ -615,8 +578,8 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
       r[3 + j] = (float)(u - uh);
       e2[j] = v[1][j] - v[0][j];
       e3[j] = v[2][j] - v[0][j];
-      r[6 + j] = (float)(e2[j] / g.L[j]);
-      r[9 + j] = (float)(e3[j] / g.L[j]);
+      r[6 + j] = (float)(TWO_PI_D * e2[j] / g.L[j]);
+      r[9 + j] = (float)(TWO_PI_D * e3[j] / g.L[j]);
       a[j] = v[1][j] - c[j];
       b[j] = v[2][j] - c[j];
     }
@@ -624,7 +587,7 @@ __global__ void __launch_bounds__(PREP_T) k_prep_tris(GridC g, const float* __re
                          sgn * (e2[0] * e3[1] - e2[1] * e3[0])};
     const double twoA = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     if (MODE == 0) {
-      for (int j = 0; j < 3; ++j) r[12 + j] = (float)(wt * n[j] / (g.L[j] * TWO_PI_D * TWO_PI_D));
+      for (int j = 0; j < 3; ++j) r[12 + j] = (float)(wt * n[j] / g.L[j]);
     } else {
       r[12] = (float)(wt * twoA);
       r[13] = 0.0f;
@@ -668,15 +631,14 @@ constexpr int SWEEP_T = 256;
 // strip-ordered triangles.  Each triangle adds one vertex: its phase factor
 // is computed, the other two are carried over from the previous triangle of
 // the strip.  Pairs are evaluated in closed (Lagrange) form,
-//   f = (-(b-a) E1 + b E2 - a E3) / (4 pi^2 a b (b-a)),
-// E_p = e^{-2 pi i t_p}, a and b the phases of vertices 2 and 3 relative to
-// vertex 1 (all in revolutions).  Pairs with a node gap below FWD_LAG_GAP or a
-// spread below one radian are queued in LDS and evaluated by dd3_acc on full
+//   f = (-(b-a) E1 + b E2 - a E3) / (a b (b-a)),
+// E_p = e^{-2 pi i t_p} (t_p in revolutions), a and b the phases of vertices
+// 2 and 3 relative to vertex 1 in radians.  Pairs with a node gap below
+// FWD_LAG_GAP_RAD or a spread below one radian are queued in LDS and
+// evaluated by dd3_acc on full
 // waves after every FWD_TQ triangles; their sums collect in an LDS row per
 // entry and are added to the register sums at the end.
-constexpr float FWD_LAG_GAP = 0.005f;
-constexpr float INV_4PI2_F = 0.025330295910584444f;   // 1 / (4 pi^2)
-constexpr float FOUR_PI2_F = 39.47841760435743f;       // 4 pi^2
+constexpr float FWD_LAG_GAP_RAD = 0.031415926535897934f;   // 0.005 rev
 constexpr int FWD_TQ = 4;   // triangles whose queued pairs share one pass
 
 // Queued pairs of FWD_TQ consecutive triangles share one pass.  Within a pass
@@ -723,7 +685,7 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
 #pragma unroll
     for (int j = 0; j < FWD_J; ++j) {
       float d2, d3;
-      rel_phases(kx[j], ky[j], kz[j], r, d2, d3);
+      rel_phases_rev(kx[j], ky[j], kz[j], r, d2, d3);
       const float t1 = vertex3_phase(kx[j], ky[j], kz[j], r) - d3;
       const float q1 = wrap(-t1), q2 = wrap(-(t1 + d2));
       Xr[j] = __builtin_amdgcn_cosf(q1);
@@ -742,10 +704,10 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
-    const bool close = mn < FWD_LAG_GAP, small = mx < SERIES_REV;
+    const bool close = mn < FWD_LAG_GAP_RAD, small = mx < SERIES_RAD;
     const bool fast = !close && !small;
-    // the volume weight k.n carries the 1 / (4 pi^2) of the record's normal
-    const float wt = MODE == 0 ? fmaf(kz[j], r[14], fmaf(ky[j], r[13], kx[j] * r[12])) : r[12] * INV_4PI2_F;
+    // with the relative phases in radians the Lagrange quotient is f_T itself
+    const float wt = MODE == 0 ? fmaf(kz[j], r[14], fmaf(ky[j], r[13], kx[j] * r[12])) : r[12];
     const float kk = fast ? wt * __builtin_amdgcn_rcpf(a * b * c) : 0.0f;
     const float tr = fmaf(-c, Xr[j], fmaf(b, Yr[j], -a * Nr));
     const float ti = fmaf(-c, Xi[j], fmaf(b, Yi[j], -a * Ni));
@@ -803,7 +765,7 @@ __device__ __forceinline__ void fwd_lanes_flush(const float* r, const float4* __
       const float4 k = kf[ew + 64 * jj + ll];
       float t1, d2, d3;
       tri_phases(k.x, k.y, k.z, rp, t1, d2, d3);
-      const float wt = MODE == 0 ? fmaf(k.z, rp[14], fmaf(k.y, rp[13], k.x * rp[12])) * FOUR_PI2_F : rp[12];
+      const float wt = MODE == 0 ? fmaf(k.z, rp[14], fmaf(k.y, rp[13], k.x * rp[12])) : rp[12];
       if (KIND == 0)
         dd3_acc_series(t1, d2, d3, wt, fr, fi);
       else if (KIND == 1)
@@ -1111,9 +1073,21 @@ struct VjpRing {
   int head, tail, prev_end;
 };
 
+// One gradient pair in closed form (caller checks the gaps, see LAG_GAP_RAD).
+// Nodes z_p = -2 pi i t_p with t = (t1, t1 + a, t1 + b); with
+// alpha = 1/(2 pi a), beta = 1/(2 pi b), gamma = 1/(2 pi (b - a)) the divided
+// difference is the Lagrange sum T0 + T1 + T2,
+//   T0 = -alpha beta E0,  T1 = alpha gamma E1,  T2 = -beta gamma E2   (E_p = e^{z_p}),
+// and its derivatives in the nodes (the repeated-node DD4 of Eq. 10) are
+//   DD4_0 = T0 + i[(alpha+beta) T0 + alpha T1 + beta T2]
+//   DD4_1 = T1 + i[(gamma-alpha) T1 - alpha T0 + gamma T2]
+//   DD4_2 = T2 - i[(beta+gamma) T2 + beta T0 + gamma T1].
+// The adjoint weight enters through its modulus and phase, W E_p =
+// |W| e^{-2 pi i (t_p - phi_W)}, so no complex product is formed.
+//   VOLUME:  z[p] = Re(W DD4_p)          SURFACE: wf = Re(W f), z[p] = Im(W DD4_p)
 // Closed-form gradient pair from the phase factors of the three nodes with
 // the adjoint weight's phase folded in (G_p = e^{-2 pi i (t_p - phi_W)}) and
-// the relative phases a, b (see lag_pair for the formulas).  With use false
+// the relative phases a, b in radians (2 pi times the a, b above).  With use false
 // every output is exactly zero (the common factor 1 / (2 pi a b c) is
 // replaced by zero, so a vanishing gap cannot produce inf or NaN).  With AMP
 // the weight's modulus is folded into the Lagrange coefficients; without it
@@ -1125,7 +1099,7 @@ __device__ __forceinline__ void lag_pair_g(float a, float b, bool use, float amp
                                            float G1i, float G2r, float G2i, float& wf, float z[3], float& Pi) {
   const float c = b - a;
   const float ab = a * b;
-  const float rD = use ? __builtin_amdgcn_rcpf(ab * c) * INV_TWO_PI_F : 0.0f;   // 1 / (2 pi a b c)
+  const float rD = use ? __builtin_amdgcn_rcpf(ab * c) : 0.0f;   // 1 / (a b c), radians
   const float al = b * c * rD, be = a * c * rD, ga = ab * rD;
   float k0, k1, k2;
   if (AMP) {
@@ -1167,8 +1141,8 @@ constexpr bool vjp_amp_in_coeffs() {
 // that need the stable scheme are appended to the wave's ring of queued pairs
 // (ring positions tail.., tagged with the triangle's parity).  The fused sweep
 // (FWD) also adds the pair's forward value, weighted like the forward sweep's
-// (k.n with the closed form's 1/(4 pi^2) for the volume density, 2A for the
-// surface density), to Fr + i Fi in the weight's phase frame.
+// (k.n / L for the volume density, 2A for the surface density), to Fr + i Fi
+// in the weight's phase frame.
 template <int MODE, int J, bool FWD, bool OPQ>
 __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int tag, const float (&kx)[J],
                                                const float (&ky)[J], const float (&kz)[J], const float (&amp)[J],
@@ -1177,18 +1151,31 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
                                                float tpz, int lane, uint16_t (*ring)[vjp_ring<J>()],
                                                VjpRing (&rq)[2], float (&acc)[MODE == 0 ? 3 : 10]) {
   constexpr bool AMP = vjp_amp_in_coeffs<MODE, FWD>();
-  constexpr int NR = MODE == 0 ? (FWD ? 15 : 12) : 12;
+  constexpr int NR = MODE == 0 ? (FWD ? 16 : 12) : 12;
+  // the record in VGPRs: FP32 instructions with all operands in VGPRs issue
+  // faster than those reading an SGPR, and vector loads of one address for
+  // the whole wave (one cache line) cost no ALU slots, unlike per-value copies
+  // from scalar registers; the zero made opaque keeps the loads vector loads
   float rvg[NR];
   if (MODE == 0) {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    const float4* p4 = reinterpret_cast<const float4*>(r) + z;
 #pragma unroll
-    for (int i = 0; i < NR; ++i) rvg[i] = to_vgpr(r[i]);
+    for (int i = 0; i < NR / 4; ++i) {
+      const float4 q = p4[i];
+      rvg[4 * i] = q.x;
+      rvg[4 * i + 1] = q.y;
+      rvg[4 * i + 2] = q.z;
+      rvg[4 * i + 3] = q.w;
+    }
   }
   const float* rv = MODE == 0 ? rvg : r;
   if (start) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float d2, d3;
-      rel_phases(kx[j], ky[j], kz[j], rv, d2, d3);
+      rel_phases_rev(kx[j], ky[j], kz[j], rv, d2, d3);
       const float r1 = vertex3_phase(kx[j], ky[j], kz[j], rv) - d3 - phw[j];
       const float q1 = wrap(-r1), q2 = wrap(-(r1 + d2));
       Xr[j] = __builtin_amdgcn_cosf(q1);
@@ -1206,7 +1193,7 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
-    const bool close = mn < LAG_GAP, small = mx < SERIES_REV;
+    const bool close = mn < LAG_GAP_RAD, small = mx < SERIES_RAD;
     const bool fast = !close && !small;
     float wf = 0.0f, z[3], Pi;
     lag_pair_g<MODE, AMP>(a, b, fast, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z, Pi);
@@ -1311,7 +1298,7 @@ __device__ __forceinline__ void vjp_lanes_pass(const uint16_t* ring, int head, i
     }
     if (FWD) {
       const float wt =
-          MODE == 0 ? fmaf(A.z, r[14], fmaf(A.y, r[13], A.x * r[12])) * FOUR_PI2_F : r[12];
+          MODE == 0 ? fmaf(A.z, r[14], fmaf(A.y, r[13], A.x * r[12])) : r[12];
       ffr = wt * fr;
       ffi = wt * fi;
       fact = true;
@@ -1490,9 +1477,7 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
       __syncthreads();
     }
     if (FWD) {
-      // back from the weight's phase frame (multiply by e^{-2 pi i phi_W}); the
-      // volume density's closed form carries 4 pi^2 (the forward sweep's scaling)
-      constexpr float FS = MODE == 0 ? FOUR_PI2_F : 1.0f;
+      // back from the weight's phase frame (multiply by e^{-2 pi i phi_W})
       wave_lds_sync();
 #pragma unroll
       for (int j = 0; j < J; ++j) {
@@ -1502,7 +1487,7 @@ __device__ __forceinline__ void vjp_lanes_tile(const float* __restrict__ rec, in
           const float cq = __builtin_amdgcn_cosf(q), sq = __builtin_amdgcn_sinf(q);
           const float ur = fmaf(Fr[j], cq, Fi[j] * sq), ui = fmaf(Fi[j], cq, -Fr[j] * sq);
           const float2 qb = L.fb[w][64 * j + lane];
-          fpart_row[e] = make_float2(fmaf(FS, ur, qb.x), fmaf(FS, ui, qb.y));
+          fpart_row[e] = make_float2(ur + qb.x, ui + qb.y);
         }
       }
     }
