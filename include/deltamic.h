@@ -327,7 +327,10 @@ dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* st
  * workspace: band-sized partials, spectra, FFT buffers), and launches them
  * as one batch (the dm_batch_run machinery, workspace from the stream-ordered
  * allocator); requests that arrive meanwhile join the next batch, which runs
- * while the earlier ones are still on the GPU.  Results are bitwise
+ * while the earlier ones are still on the GPU.  A request of at least 5e8
+ * (band entry, triangle) pairs runs its own sweep launches after the batch's
+ * shared launch; unless max_batch requests are waiting, it starts only when
+ * nothing else is in flight and nothing starts beside it.  Results are bitwise
  * independent of which requests shared a batch.  Thread-safe: any thread may
  * submit and poll. */
 typedef struct dm_server dm_server;

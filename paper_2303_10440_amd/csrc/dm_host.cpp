@@ -1577,6 +1577,7 @@ struct ServeReq {
   dm_status status = DM_ERR_BUSY;   // DM_ERR_BUSY while pending
   int32_t batch = 0;
   double t_submit = 0.0, t_launch = 0.0, t_done = 0.0;
+  bool large = false;     // planned once: runs its own sweep launches
 };
 
 struct Inflight {
@@ -1587,6 +1588,7 @@ struct Inflight {
   size_t bytes = 0;
   int slot = 0;
   void* mem = nullptr;    // fallback allocation when the stream-ordered pool is unavailable
+  bool solo = false;      // holds a request that runs its own sweep launches
 };
 
 }  // namespace
@@ -1665,8 +1667,11 @@ void retire_locked(dm_server* S) {
 
 // Plans and launches one batch from `take` on stream slot `slot`.  Requests
 // that do not fit the budget next to the in-flight batches go back to the
-// front of the queue.
-size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
+// front of the queue.  Unless there is a backlog, a large request runs in a
+// batch of its own on an idle device: one first in `take` on an idle device
+// is launched alone, otherwise the batch ends before it; what follows it in
+// `take` goes back.
+size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take, bool idle, bool backlog) {
   hipStream_t s = S->streams[(size_t)slot];
   std::vector<ReqPlan> P;
   std::vector<uint64_t> ids;
@@ -1694,6 +1699,21 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
       failed.push_back({take[i], st});
       continue;
     }
+    bool last = false;
+    if (pl.direct) {
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->reqs[take[i]].large = true;
+      }
+      if (!backlog) {
+        if (!idle || !P.empty()) {
+          unpin_band(h, &pl.g, &pl.psf);
+          back.assign(take.begin() + (long)i, take.end());
+          break;
+        }
+        last = true;
+      }
+    }
     const size_t need = align_up(pl.bytes) + 4096;
     if (budget && need > budget) {
       unpin_band(h, &pl.g, &pl.psf);
@@ -1713,6 +1733,10 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
     used += need;
     P.push_back(pl);
     ids.push_back(take[i]);
+    if (last) {
+      back.assign(take.begin() + (long)i + 1, take.end());
+      break;
+    }
   }
   Inflight b;
   dm_status st = DM_OK;
@@ -1757,6 +1781,7 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take) {
     if (st == DM_OK && b.ev) {
       b.tickets = ids;
       b.slot = slot;
+      for (const auto& pl : P) b.solo = b.solo || pl.direct;
       for (uint64_t id : ids) S->reqs[id].t_launch = t;
       S->inflight.push_back(b);
       S->busy[(size_t)slot] = true;
@@ -1792,14 +1817,29 @@ void serve_loop(dm_server* S) {
       }
     const bool mem_free = !S->cfg.hbm_budget_bytes || S->inflight.empty() ||
                           S->inflight_bytes < S->cfg.hbm_budget_bytes;
-    if (slot >= 0 && !S->queue.empty() && mem_free) {
+    // Large requests (their own sweep launches) run alone unless a backlog of
+    // a full batch has built up: nothing new starts beside one, and one starts
+    // only on an idle device.  Work sharing the compute units with a large
+    // request stretches the longest latencies, and a large request started
+    // beside a batch stretches that batch; requests that wait are batched
+    // afterwards.
+    bool solo = false;
+    for (const Inflight& b : S->inflight) solo = solo || b.solo;
+    const bool backlog = (int)S->queue.size() >= S->cfg.max_batch;
+    const bool idle = S->inflight.empty();
+    bool head_large = false;
+    if (!S->queue.empty()) {
+      auto it = S->reqs.find(S->queue.front());
+      head_large = it != S->reqs.end() && it->second.large;
+    }
+    if (slot >= 0 && !S->queue.empty() && mem_free && (!solo || backlog) && (!head_large || idle || backlog)) {
       std::vector<uint64_t> take;
       while ((int)take.size() < S->cfg.max_batch && !S->queue.empty()) {
         take.push_back(S->queue.front());
         S->queue.pop_front();
       }
       lk.unlock();
-      const size_t handled = launch_batch(S, slot, std::move(take));
+      const size_t handled = launch_batch(S, slot, std::move(take), idle, backlog);
       lk.lock();
       // nothing fitted next to the in-flight work: wait for a batch to finish
       if (handled == 0) S->cv_work.wait_for(lk, std::chrono::microseconds(20));
