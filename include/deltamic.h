@@ -270,7 +270,10 @@ dm_status dm_mesh_transform_noalloc(dm_handle* h, const dm_mesh* mesh, const dm_
 /* One request of a batch: the forward render and/or gradient of one mesh on
  * its own grid with its own PSF (same meaning as dm_render_vjp's arguments).
  * dL_dimage_dev may be NULL for a forward-only request; any output may be
- * NULL, but each request must ask for at least one. */
+ * NULL, but each request must ask for at least one.  With otf_dev set, the
+ * PSF is that tabulated OTF (as in dm_render_otf, band from grid.band_tau)
+ * and psf is ignored; such a request has no PSF gradient (dL_dsigma_dev
+ * must be NULL: DM_ERR_ARG). */
 typedef struct {
   dm_mesh mesh;
   dm_psf psf;
@@ -279,6 +282,7 @@ typedef struct {
   float* image_dev;             /* [n0][n1][n2] or NULL */
   float* dL_dverts_dev;         /* [n_verts][3] or NULL (needs dL_dimage_dev) */
   float* dL_dsigma_dev;         /* [6] or NULL (needs dL_dimage_dev) */
+  const void* otf_dev;          /* complex64 [n0][n1][n2/2+1] (dm_render_otf's table) or NULL */
 } dm_request;
 
 /* Rendering with a tabulated PSF (paper Sec. 3.2 and Sec. 7: measured or
@@ -293,8 +297,9 @@ typedef struct {
  * transform of the grid's density mode, as in dm_render.  The band is rebuilt
  * on every call (the table may change), which synchronises the stream once.
  * dm_render_otf_vjp returns dL/dverts (and optionally the image) for a given
- * dL/dimage, the band held fixed; there is no PSF gradient.  Not available
- * through dm_batch_run or the server.  Errors as dm_render. */
+ * dL/dimage, the band held fixed; there is no PSF gradient.  Batches and the
+ * server take tabulated OTFs per request (dm_request.otf_dev,
+ * dm_serve_request.otf_dev).  Errors as dm_render. */
 dm_status dm_render_otf(dm_handle* h, const dm_mesh* mesh, const void* otf, const dm_grid* g, float* image_out,
                         void* stream);
 dm_status dm_render_otf_vjp(dm_handle* h, const dm_mesh* mesh, const void* otf, const dm_grid* g,
@@ -307,13 +312,14 @@ dm_status dm_render_otf_vjp(dm_handle* h, const dm_mesh* mesh, const void* otf, 
  * shared queue, longest first; the small per-request steps (band, mesh prep,
  * FFTs, adjoint weights, reductions) run around them on the same stream.  A
  * request with dL_dimage and both an image (or dL_dsigma) and dL_dverts runs
- * the tiles of dm_render_vjp's fused sweep, so its outputs are bitwise
- * dm_render_vjp's; forward-only and gradient-only requests have tiles of
- * their own (same results as the single calls up to float32 summation
- * order).  Each request's tiles and summation order depend on that request
- * alone, so its results are bitwise the same whatever else is in the batch.
- * All validation happens before anything is enqueued; on error no output is
- * written. */
+ * dm_render_vjp's fused sweep in tiles of at least 4M (entry, triangle)
+ * pairs; forward-only and gradient-only requests have tiles of their own.
+ * Results equal the single calls' up to float32 summation order.  Each
+ * request's tiles and summation order depend on that request alone, so its
+ * results are bitwise the same whatever else is in the batch.  A request with
+ * a tabulated OTF counts its band while the batch is planned (one stream
+ * synchronisation) and builds it in its own workspace.  All validation
+ * happens before anything is enqueued; on error no output is written. */
 dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* stream);
 
 /* --------------------------------------------------------------- serving */
@@ -350,6 +356,8 @@ typedef struct {
   float* image_dev;           /* outputs as in dm_request; device buffers owned by */
   float* dL_dverts_dev;       /* the caller and kept valid until dm_poll reports  */
   float* dL_dsigma_dev;       /* the request finished                            */
+  const void* otf_dev;        /* tabulated OTF as in dm_request (psf ignored), or */
+                              /* NULL; kept valid and unchanged until finished   */
 } dm_serve_request;
 
 typedef struct {

@@ -63,7 +63,8 @@ class CServerConfig(ctypes.Structure):
 
 class CServeRequest(ctypes.Structure):
     _fields_ = [("mesh_id", ctypes.c_int32), ("psf", CPsf), ("grid", CGrid), ("dL_dimage_dev", ctypes.c_void_p),
-                ("image_dev", ctypes.c_void_p), ("dL_dverts_dev", ctypes.c_void_p), ("dL_dsigma_dev", ctypes.c_void_p)]
+                ("image_dev", ctypes.c_void_p), ("dL_dverts_dev", ctypes.c_void_p), ("dL_dsigma_dev", ctypes.c_void_p),
+                ("otf_dev", ctypes.c_void_p)]
 
 
 class CServeResult(ctypes.Structure):
@@ -78,7 +79,8 @@ class CServerStats(ctypes.Structure):
 
 class CRequest(ctypes.Structure):
     _fields_ = [("mesh", CMesh), ("psf", CPsf), ("grid", CGrid), ("dL_dimage_dev", ctypes.c_void_p),
-                ("image_dev", ctypes.c_void_p), ("dL_dverts_dev", ctypes.c_void_p), ("dL_dsigma_dev", ctypes.c_void_p)]
+                ("image_dev", ctypes.c_void_p), ("dL_dverts_dev", ctypes.c_void_p), ("dL_dsigma_dev", ctypes.c_void_p),
+                ("otf_dev", ctypes.c_void_p)]
 
 
 _lib = None
@@ -456,13 +458,21 @@ def render_otf_vjp(h: Handle, verts, topo: Topology, otf, grid, dL_dimage, want_
 def batch_run(h: Handle, requests, want_image: bool = True, want_verts: bool = True, want_sigma: bool = True):
     """Runs many independent requests as one batch (dm_batch_run).
 
-    ``requests``: sequence of (verts, topo, sigma6, grid, dL_dimage or None).
+    ``requests``: sequence of (verts, topo, sigma6, grid, dL_dimage or None)
+    or (verts, topo, sigma6, grid, dL_dimage or None, otf): with a tabulated
+    OTF (complex64 half spectrum, as in render_otf) sigma6 is ignored (may be
+    None) and the request has no dL/dsigma.
     Returns a list of (image | None, dL/dverts | None, dL/dsigma | None)."""
     torch = _torch()
     n = len(requests)
     arr = (CRequest * max(n, 1))()
     outs, keep = [], []
-    for i, (verts, topo, sigma6, grid, gI) in enumerate(requests):
+    for i, req in enumerate(requests):
+        if len(req) not in (5, 6):
+            raise ValueError("a request is (verts, topo, sigma6, grid, dL_dimage[, otf])")
+        verts, topo, sigma6, grid, gI = req[:5]
+        otf = req[5] if len(req) == 6 else None
+        otf = _otf_tensor(otf, grid) if otf is not None else None
         verts = _dev_tensor(verts, torch.float32, 3, "verts")
         shape = tuple(int(x) for x in grid.n)
         if gI is not None:
@@ -471,17 +481,19 @@ def batch_run(h: Handle, requests, want_image: bool = True, want_verts: bool = T
                 raise ValueError("dL_dimage must have the grid's shape")
         img = torch.empty(shape, dtype=torch.float32, device=verts.device) if want_image else None
         dv = torch.empty_like(verts) if (want_verts and gI is not None) else None
-        ds = torch.empty(6, dtype=torch.float32, device=verts.device) if (want_sigma and gI is not None) else None
+        ds = (torch.empty(6, dtype=torch.float32, device=verts.device)
+              if (want_sigma and gI is not None and otf is None) else None)
         r = arr[i]
         r.mesh = _mesh(verts, topo)
-        r.psf = _psf(sigma6)
+        r.psf = _psf(sigma6) if otf is None else CPsf()
+        r.otf_dev = otf.data_ptr() if otf is not None else None
         r.grid = _grid(grid)
         r.dL_dimage_dev = gI.data_ptr() if gI is not None else None
         r.image_dev = img.data_ptr() if img is not None else None
         r.dL_dverts_dev = dv.data_ptr() if dv is not None else None
         r.dL_dsigma_dev = ds.data_ptr() if ds is not None else None
         outs.append((img, dv, ds))
-        keep.append((verts, gI))
+        keep.append((verts, gI, otf))
     _check(_load().dm_batch_run(h.ptr, n, ctypes.cast(arr, ctypes.c_void_p), _stream(h.device)), "dm_batch_run")
     return outs
 
@@ -520,14 +532,22 @@ class Server:
     def mesh_remove(self, mesh_id: int):
         _check(_load().dm_server_mesh_remove(self._s, int(mesh_id)), "dm_server_mesh_remove")
 
-    def submit(self, mesh_id: int, sigma6, grid, dL_dimage=None, image=None, dverts=None, dsigma=None) -> int:
-        """Queues a request; the tensors must stay alive until poll() reports it."""
+    def submit(self, mesh_id: int, sigma6, grid, dL_dimage=None, image=None, dverts=None, dsigma=None,
+               otf=None) -> int:
+        """Queues a request; the tensors must stay alive until poll() reports it.
+        ``otf``: a tabulated OTF (complex64 half spectrum on the device, as in
+        render_otf) instead of sigma6 (then ignored; no dsigma)."""
         r = CServeRequest()
         r.mesh_id = int(mesh_id)
-        r.psf = _psf(sigma6)
+        r.psf = _psf(sigma6) if otf is None else CPsf()
         r.grid = _grid(grid)
         p = lambda t: t.data_ptr() if t is not None else None
         r.dL_dimage_dev, r.image_dev, r.dL_dverts_dev, r.dL_dsigma_dev = p(dL_dimage), p(image), p(dverts), p(dsigma)
+        if otf is not None:
+            o = _otf_tensor(otf, grid)
+            if o is not otf:
+                raise ValueError("otf must be contiguous (the server reads it when the request runs)")
+            r.otf_dev = o.data_ptr()
         t = ctypes.c_uint64()
         _check(_load().dm_submit(self._s, ctypes.byref(r), ctypes.byref(t)), "dm_submit")
         return int(t.value)

@@ -349,29 +349,68 @@ dm_status get_band(dm_handle* h, const dm_grid* g, const dm_psf* p, hipStream_t 
   return DM_OK;
 }
 
-// Band of a tabulated OTF (half spectrum, device): rebuilt on every call since
-// the table may change between calls; its memory is reused.  Synchronises s.
+// Slots of the band build: 4x4x4 bricks of the half spectrum.
+int64_t band_slots(const GridC& gc) {
+  return (int64_t)((gc.n0 + 3) / 4) * ((gc.n1 + 3) / 4) * ((gc.n2h + 3) / 4) * 64;
+}
+
+double otf_tau2(const dm_grid* g) {
+  const double tau = (double)(g->band_tau > 0.0f ? g->band_tau : 0.0f);
+  return tau * tau;
+}
+
+// Layout of a tabulated-OTF band: entry arrays, then the position map.
+struct OtfBandLayout {
+  size_t o_kf = 0, o_w = 0, o_pos = 0, o_map = 0;
+  void take(Carver& c, int64_t n_entries, int64_t n_pos) {
+    const int64_t ne = std::max<int64_t>(n_entries, 1);
+    o_kf = c.take<float4>(ne);
+    o_w = c.take<float>(ne);
+    o_pos = c.take<int32_t>(ne);
+    o_map = c.take<int32_t>(n_pos);
+  }
+  void bind(char* base, BandDev& b) const {
+    b.kf = reinterpret_cast<float4*>(base + o_kf);
+    b.wgt = reinterpret_cast<float*>(base + o_w);
+    b.pos = reinterpret_cast<int32_t*>(base + o_pos);
+    b.map = reinterpret_cast<int32_t*>(base + o_map);
+  }
+};
+
+// Counts the band of a tabulated OTF, with the per-slot counts and offsets in
+// the workspace (cnt, off) for a fill that follows on the same stream.
+// Synchronises s.
+dm_status count_otf_band(dm_handle* h, const dm_grid* g, const float2* otf, hipStream_t s, int64_t* total,
+                         int32_t** cnt, int32_t** off) {
+  const GridC gc = make_gridc(g);
+  const int64_t n_slots = band_slots(gc);
+  Carver cv;
+  const size_t o_cnt = cv.take<int32_t>(n_slots), o_off = cv.take<int32_t>(n_slots),
+               o_tmp = cv.take<int32_t>(scan_tmp_elems(n_slots)), o_tot = cv.take<int64_t>(1);
+  DM_TRY(ensure_ws(h, cv.off));
+  *cnt = at<int32_t>(h, o_cnt);
+  *off = at<int32_t>(h, o_off);
+  HIP_TRY(launch_band_count_otf(gc, otf, otf_tau2(g), *cnt, n_slots, s));
+  HIP_TRY(launch_scan(*cnt, *off, n_slots, at<int32_t>(h, o_tmp), at<int64_t>(h, o_tot), s));
+  *total = 0;
+  HIP_TRY(hipMemcpyAsync(total, at<int64_t>(h, o_tot), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DM_OK;
+}
+
+// Band of a tabulated OTF (half spectrum, device) for a single call: rebuilt
+// on every call since the table may change between calls; its memory is the
+// handle's and is reused.  Synchronises s.
 dm_status get_otf_band(dm_handle* h, const dm_grid* g, const float2* otf, hipStream_t s, BandDev* out) {
   const GridC gc = make_gridc(g);
   const int64_t n_pos = (int64_t)gc.n0 * gc.n1 * gc.n2h;
-  const int64_t n_slots = (int64_t)((gc.n0 + 3) / 4) * ((gc.n1 + 3) / 4) * ((gc.n2h + 3) / 4) * 64;
-  const int64_t ntmp = scan_tmp_elems(n_slots);
-  Carver cv;
-  const size_t o_cnt = cv.take<int32_t>(n_slots), o_off = cv.take<int32_t>(n_slots), o_tmp = cv.take<int32_t>(ntmp),
-               o_tot = cv.take<int64_t>(1);
-  DM_TRY(ensure_ws(h, cv.off));
-  int32_t* cnt = at<int32_t>(h, o_cnt);
-  int32_t* off = at<int32_t>(h, o_off);
-  const double tau = (double)(g->band_tau > 0.0f ? g->band_tau : 0.0f);
-  HIP_TRY(launch_band_count_otf(gc, otf, tau * tau, cnt, n_slots, s));
-  HIP_TRY(launch_scan(cnt, off, n_slots, at<int32_t>(h, o_tmp), at<int64_t>(h, o_tot), s));
+  const int64_t n_slots = band_slots(gc);
   int64_t total = 0;
-  HIP_TRY(hipMemcpyAsync(&total, at<int64_t>(h, o_tot), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  int32_t *cnt = nullptr, *off = nullptr;
+  DM_TRY(count_otf_band(h, g, otf, s, &total, &cnt, &off));
   Carver bc;
-  const int64_t ne = std::max<int64_t>(total, 1);
-  const size_t o_kf = bc.take<float4>(ne), o_w = bc.take<float>(ne), o_pos = bc.take<int32_t>(ne),
-               o_map = bc.take<int32_t>(n_pos);
+  OtfBandLayout bl;
+  bl.take(bc, total, n_pos);
   BandEntry& be = h->otf_band;
   if (be.bytes < bc.off) {
     dev_free(h, be.mem, be.bytes);
@@ -380,15 +419,11 @@ dm_status get_otf_band(dm_handle* h, const dm_grid* g, const float2* otf, hipStr
     DM_TRY(dev_alloc(h, &be.mem, bc.off));
     be.bytes = bc.off;
   }
-  char* base = static_cast<char*>(be.mem);
   be.dev.n_entries = total;
   be.dev.n_pos = n_pos;
-  be.dev.kf = reinterpret_cast<float4*>(base + o_kf);
-  be.dev.wgt = reinterpret_cast<float*>(base + o_w);
-  be.dev.pos = reinterpret_cast<int32_t*>(base + o_pos);
-  be.dev.map = reinterpret_cast<int32_t*>(base + o_map);
+  bl.bind(static_cast<char*>(be.mem), be.dev);
   be.dev.otf = otf;
-  HIP_TRY(launch_band_fill_otf(gc, otf, tau * tau, cnt, off, n_slots, be.dev, s));
+  HIP_TRY(launch_band_fill_otf(gc, otf, otf_tau2(g), cnt, off, n_slots, be.dev, s));
   *out = be.dev;
   return DM_OK;
 }
@@ -631,6 +666,9 @@ struct ReqPlan {
   const float* spec_in = nullptr;
   float* spec_out = nullptr;
   const float2* otf = nullptr;   // tabulated OTF (half spectrum) instead of the Gaussian PSF
+  bool otf_ws = false;   // the OTF band lives in this request's workspace, built by stage_pre
+  OtfBandLayout obl;
+  size_t o_bcnt = 0, o_boff = 0, o_btmp = 0, o_btot = 0;
   int mode = 0, nt = 0, nv = 0, nc = 3, prep_blocks = 1, adj_blocks = 1;
   int64_t nvox = 0, nE = 0;
   bool want_vjp = false, need_spec = false, empty = false, pinned = false;
@@ -691,7 +729,19 @@ dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch, doub
   P.nv = P.m->n_verts;
   P.nvox = (int64_t)P.g.n[0] * P.g.n[1] * P.g.n[2];
   P.want_vjp = P.dLdI && (P.dV || P.dS);
-  if (P.otf) {
+  if (P.otf && batch) {
+    // a batch holds several tables at once: count now (for the plan), build
+    // the band in the request's own workspace with its pre-steps
+    int64_t total = 0;
+    int32_t *cnt = nullptr, *off = nullptr;
+    DM_TRY(count_otf_band(h, &P.g, P.otf, s, &total, &cnt, &off));
+    P.b = BandDev{};
+    P.b.n_entries = total;
+    P.b.n_pos = (int64_t)P.gc.n0 * P.gc.n1 * P.gc.n2h;
+    P.b.otf = P.otf;
+    P.otf_ws = true;
+    P.pinned = false;
+  } else if (P.otf) {
     DM_TRY(get_otf_band(h, &P.g, P.otf, s, &P.b));
     P.pinned = false;
   } else {
@@ -735,9 +785,24 @@ dm_status plan_request(dm_handle* h, ReqPlan& P, hipStream_t s, bool batch, doub
     P.o_red = vjp_v ? cv.take<float>((size_t)P.nc * P.nt) : 0;
     P.o_rtmp = vjp_v ? cv.take<float>((size_t)vjp_reduce_groups(P.vsp.n_chunks) * P.nc * P.nt) : 0;
     P.o_R = cv.take<double>(1);
+    if (P.otf_ws) {
+      const int64_t n_slots = band_slots(P.gc);
+      P.obl.take(cv, P.nE, P.b.n_pos);
+      P.o_bcnt = cv.take<int32_t>(n_slots);
+      P.o_boff = cv.take<int32_t>(n_slots);
+      P.o_btmp = cv.take<int32_t>(scan_tmp_elems(n_slots));
+      P.o_btot = cv.take<int64_t>(1);
+    }
   }
   P.bytes = cv.off;
   return DM_OK;
+}
+
+// Drops the pin a batch request holds on its cached band (none for a
+// tabulated OTF, whose band is the request's own).
+void release_band(dm_handle* h, ReqPlan& P) {
+  if (P.pinned) unpin_band(h, &P.g, &P.psf);
+  P.pinned = false;
 }
 
 const float2* spectrum_of(const ReqPlan& P) {
@@ -745,7 +810,14 @@ const float2* spectrum_of(const ReqPlan& P) {
   return reinterpret_cast<const float2*>(P.spec_in);
 }
 
-// Mesh prep and, for the gradient, FFT of dL/dI and adjoint weights.
+// Points the band of a request whose band lives in its workspace at that
+// workspace (once P.base is set).
+void bind_band(ReqPlan& P) {
+  if (P.otf_ws && !P.empty) P.obl.bind(P.base, P.b);
+}
+
+// Mesh prep and, for the gradient, FFT of dL/dI and adjoint weights; the
+// band first when it lives in the request's workspace.
 dm_status stage_pre(dm_handle* h, ReqPlan& P, hipStream_t s) {
   if (P.empty) {
     DM_TRY(zero_fill(P.image, P.nvox, s));
@@ -753,6 +825,15 @@ dm_status stage_pre(dm_handle* h, ReqPlan& P, hipStream_t s) {
     DM_TRY(zero_fill(P.dV, 3 * (int64_t)P.nv, s));
     DM_TRY(zero_fill(P.dS, 6, s));
     return DM_OK;
+  }
+  if (P.otf_ws) {
+    // the same count as at planning (the table is read again), then the fill
+    const int64_t n_slots = band_slots(P.gc);
+    int32_t* cnt = P.ptr<int32_t>(P.o_bcnt);
+    int32_t* off = P.ptr<int32_t>(P.o_boff);
+    HIP_TRY(launch_band_count_otf(P.gc, P.otf, otf_tau2(&P.g), cnt, n_slots, s));
+    HIP_TRY(launch_scan(cnt, off, n_slots, P.ptr<int32_t>(P.o_btmp), P.ptr<int64_t>(P.o_btot), s));
+    HIP_TRY(launch_band_fill_otf(P.gc, P.otf, otf_tau2(&P.g), cnt, off, n_slots, P.b, s));
   }
   HIP_TRY(launch_mesh_prep(P.mode, P.gc, P.m->verts_dev, P.nv, P.m->topo->faces, P.m->topo->flags, P.m->topo->weights,
                            P.nt, P.ptr<float>(P.o_rec),
@@ -892,11 +973,13 @@ dm_status render_impl(dm_handle* h, const dm_mesh* m, const dm_psf* psf, const d
 
 dm_status check_request(const dm_request& r, int i) {
   DM_TRY(check_grid(&r.grid));
-  DM_TRY(check_psf(&r.psf));
+  if (!r.otf_dev) DM_TRY(check_psf(&r.psf));
   DM_TRY(check_mesh(&r.mesh, r.grid.mode));
   if (!r.image_dev && !r.dL_dverts_dev && !r.dL_dsigma_dev) return fail(DM_ERR_ARG, "request %d: no output", i);
   if ((r.dL_dverts_dev || r.dL_dsigma_dev) && !r.dL_dimage_dev)
     return fail(DM_ERR_ARG, "request %d: gradients need dL_dimage", i);
+  if (r.otf_dev && r.dL_dsigma_dev)
+    return fail(DM_ERR_ARG, "request %d: no PSF gradient with a tabulated OTF", i);
   return DM_OK;
 }
 
@@ -908,6 +991,7 @@ void fill_plan(ReqPlan& P, const dm_request& r) {
   P.image = r.image_dev;
   P.dV = r.dL_dimage_dev ? r.dL_dverts_dev : nullptr;
   P.dS = r.dL_dimage_dev ? r.dL_dsigma_dev : nullptr;
+  P.otf = static_cast<const float2*>(r.otf_dev);
 }
 
 // Device layout of a batch: request regions, then the sorted work list, the
@@ -1044,6 +1128,7 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
   int n_direct = 0;
   for (size_t i = 0; i < n; ++i) {
     P[i].base = base + L.off[i];
+    bind_band(P[i]);
     L.reqs[i] = sweep_req(P[i]);
     if (P[i].direct && !P[i].empty) ++n_direct;
   }
@@ -1437,12 +1522,10 @@ dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* st
   CallScope call(h, s);
   DM_TRY(call.begin());
   std::vector<ReqPlan> P((size_t)n);
-  int planned = 0;
   dm_status st = DM_OK;
   for (int i = 0; i < n && st == DM_OK; ++i) {
     fill_plan(P[i], reqs[i]);
     st = plan_request(h, P[i], s, true);
-    if (st == DM_OK) planned = i + 1;
   }
   BatchLayout L;
   if (st == DM_OK) {
@@ -1450,7 +1533,7 @@ dm_status dm_batch_run(dm_handle* h, int32_t n, const dm_request* reqs, void* st
     st = ensure_ws(h, L.total);
   }
   if (st == DM_OK) st = enqueue_batch(h, P, L, static_cast<char*>(h->ws), s, &h->aux);
-  for (int i = 0; i < planned; ++i) unpin_band(h, &P[i].g, &P[i].psf);
+  for (auto& pl : P) release_band(h, pl);
   if (st != DM_OK) return st;
   return call.end();
 }
@@ -1707,7 +1790,7 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take, bool idl
       }
       if (!backlog) {
         if (!idle || !P.empty()) {
-          unpin_band(h, &pl.g, &pl.psf);
+          release_band(h, pl);
           back.assign(take.begin() + (long)i, take.end());
           break;
         }
@@ -1716,17 +1799,17 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take, bool idl
     }
     const size_t need = align_up(pl.bytes) + 4096;
     if (budget && need > budget) {
-      unpin_band(h, &pl.g, &pl.psf);
+      release_band(h, pl);
       failed.push_back({take[i], DM_ERR_BUDGET});
       continue;
     }
     if (budget && inflight_bytes + used + need > budget && !P.empty()) {
-      unpin_band(h, &pl.g, &pl.psf);
+      release_band(h, pl);
       back.assign(take.begin() + (long)i, take.end());
       break;
     }
     if (budget && inflight_bytes + used + need > budget) {   // wait for memory to free up
-      unpin_band(h, &pl.g, &pl.psf);
+      release_band(h, pl);
       back.assign(take.begin() + (long)i, take.end());
       break;
     }
@@ -1776,7 +1859,7 @@ size_t launch_batch(dm_server* S, int slot, std::vector<uint64_t> take, bool idl
       S->event_pool.pop_back();
     }
     if (st == DM_OK && b.ev) st = hipEventRecord(b.ev, s) == hipSuccess ? DM_OK : DM_ERR_DEVICE;
-    for (auto& pl : P) unpin_band(h, &pl.g, &pl.psf);
+    for (auto& pl : P) release_band(h, pl);
     const double t = now_ms();
     if (st == DM_OK && b.ev) {
       b.tickets = ids;
@@ -1959,7 +2042,7 @@ dm_status dm_submit(dm_server* S, const dm_serve_request* r, uint64_t* ticket) {
   g_err.clear();
   if (!S || !r || !ticket) return fail(DM_ERR_ARG, "NULL argument");
   DM_TRY(check_grid(&r->grid));
-  DM_TRY(check_psf(&r->psf));
+  if (!r->otf_dev) DM_TRY(check_psf(&r->psf));
   std::unique_lock<std::mutex> lk(S->mu);
   if (S->stop) return fail(DM_ERR_STATE, "server is shutting down");
   auto it = S->meshes.find(r->mesh_id);
@@ -1975,6 +2058,7 @@ dm_status dm_submit(dm_server* S, const dm_serve_request* r, uint64_t* ticket) {
   q.req.image_dev = r->image_dev;
   q.req.dL_dverts_dev = r->dL_dverts_dev;
   q.req.dL_dsigma_dev = r->dL_dsigma_dev;
+  q.req.otf_dev = r->otf_dev;
   DM_TRY(check_request(q.req, 0));
   if ((int)S->queue.size() >= S->cfg.queue_capacity) return fail(DM_ERR_BUSY, "queue full");
   q.t_submit = now_ms();

@@ -236,3 +236,58 @@ def test_cfg4_sized_request_in_the_shared_launch_vs_oracle(dm, handle, ref):
     err = rel_l2(dv.cpu().numpy().astype(np.float64)[vs], want)
     say("cfg4 largest cell in the shared launch: dV rel l2 at 12 vertices", err)
     assert err < 1e-4
+
+
+def test_batch_with_tabulated_otf_requests(dm, handle, ref):
+    """Tabulated-OTF requests (aberrated tables: defocus phase, missing cone)
+    in one batch with Gaussian ones: the OTF requests match the FP64 oracle
+    (image, vertex gradient), agree with dm_render_otf_vjp to float32 rounding
+    and are bitwise a batch of themselves alone; the Gaussian requests are
+    bitwise unchanged by their company.  Each OTF request builds its band in
+    its own workspace, so two different tables on one grid coexist."""
+    import dataclasses
+
+    import torch
+    from workloads import psfs
+    c_vol = configs.cfg1(VOLUME)
+    c_surf = configs.cfg1(SURFACE)
+    g_vol = f32_grid(c_vol.grid)
+    g_surf = dataclasses.replace(f32_grid(c_surf.grid), n=(30, 31, 33), mode=SURFACE)
+    otf_a = psfs.aberrated_otf(g_vol, 1.0, 2.0, defocus=0.9, cone=1.2)
+    otf_b = psfs.aberrated_otf(g_vol, 1.2, 2.4, defocus=-0.6, cone=1.0)
+    otf_c = psfs.aberrated_otf(g_surf, 1.0, 2.0, defocus=0.9, cone=1.2)
+    rng = np.random.default_rng(41)
+    t_vol = handle.topology(c_vol.F, n_verts=len(c_vol.V))
+    t_surf = handle.topology(c_surf.F, n_verts=len(c_surf.V))
+    gauss = _requests(dm, handle, [configs.box_case(mode=VOLUME), configs.cfg1(SURFACE)], seed=42)
+    otf_dev = [dev(psfs.half_spectrum(o).astype(np.complex64)) for o in (otf_a, otf_b, otf_c)]
+    otf_reqs = [
+        (dev(c_vol.V), t_vol, None, g_vol, dev(rng.standard_normal(g_vol.n).astype(np.float32)), otf_dev[0]),
+        (dev(c_vol.V * 1.02), t_vol, None, g_vol, dev(rng.standard_normal(g_vol.n).astype(np.float32)), otf_dev[1]),
+        (dev(c_surf.V), t_surf, None, g_surf, dev(rng.standard_normal(g_surf.n).astype(np.float32)), otf_dev[2]),
+    ]
+    reqs = [otf_reqs[0], gauss[0], otf_reqs[1], gauss[1], otf_reqs[2]]
+    out = dm.batch_run(handle, reqs)
+    alone = [dm.batch_run(handle, [r])[0] for r in reqs]
+    torch.cuda.synchronize()
+    for i, (o, a) in enumerate(zip(out, alone)):
+        eq = all((x is None and y is None) or torch.equal(x, y) for x, y in zip(o, a))
+        say(f"request {i}: bitwise a batch of itself alone: {eq}")
+        assert eq
+    tables = [otf_a, otf_b, otf_c]
+    for j, i in enumerate((0, 2, 4)):
+        V, topo, _, g, G, otf = reqs[i]
+        img, dv, ds = out[i]
+        assert ds is None
+        dv1, img1 = dm.render_otf_vjp(handle, V, topo, otf, g, G, want_image=True)
+        torch.cuda.synchronize()
+        # float32 summation orders of the batch tiles and the single call
+        assert rel_l2(img.cpu().numpy(), img1.cpu().numpy()) < 1e-5
+        assert rel_l2(dv.cpu().numpy(), dv1.cpu().numpy()) < 1e-5
+        V64 = V.cpu().numpy().astype(np.float64)
+        F = c_vol.F if g.mode == VOLUME else c_surf.F
+        want = ref.render_otf(V64, F, g, tables[j].astype(np.complex128))
+        dvw = ref.render_otf_vjp(V64, F, g, tables[j].astype(np.complex128), G.cpu().numpy().astype(np.float64))
+        e_img, e_dv = rel_l2(img.cpu().numpy(), want), rel_l2(dv.cpu().numpy(), dvw)
+        say(f"otf request {i}: image {e_img:.2e} dV {e_dv:.2e} against the oracle")
+        assert e_img < 1e-5 and e_dv < 1e-4

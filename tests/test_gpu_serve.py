@@ -199,3 +199,52 @@ def test_served_large_requests_on_two_streams(dm):
             assert eq
     finally:
         srv.close()
+
+
+def test_served_tabulated_otf_requests(dm):
+    """Requests with tabulated OTFs next to Gaussian ones in the server: each
+    result is bitwise the same request run alone through dm_batch_run, and a
+    request asking for the PSF gradient with a tabulated OTF is refused at
+    submission."""
+    import torch
+    from workloads import psfs
+    say("serve tabulated OTF requests")
+    cells = _cells(3, seed=9)
+    srv = dm.Server(0, max_batch=8, max_inflight=2)
+    h = dm.Handle(0)
+    try:
+        mids = [srv.mesh_add(c.V, c.F) for c in cells]
+        bufs = [_buffers(c, 60 + i) for i, c in enumerate(cells)]
+        otfs = {}
+        for i in (0, 2):
+            g = bufs[i][0]
+            otfs[i] = torch.tensor(psfs.half_spectrum(psfs.aberrated_otf(g, 1.1, 2.2, defocus=0.7, cone=1.1))
+                                   .astype(np.complex64), device="cuda:0")
+        tickets = []
+        for i, c in enumerate(cells):
+            g, G, img, dv, ds = bufs[i]
+            if i in otfs:
+                tickets.append(srv.submit(mids[i], None, g, G, img, dv, None, otf=otfs[i]))
+            else:
+                tickets.append(srv.submit(mids[i], f32_sigma(c.sigma), g, G, img, dv, ds))
+        g0, G0, img0, dv0, _ = bufs[0]
+        with pytest.raises(dm.DeltamicError):
+            srv.submit(mids[0], None, g0, G0, torch.empty_like(img0), torch.empty_like(dv0),
+                       torch.empty(6, device="cuda:0"), otf=otfs[0])
+        res = [srv.poll(t) for t in tickets]
+        assert all(r["status"] == 0 for r in res)
+        torch.cuda.synchronize()
+        for i, c in enumerate(cells):
+            g, G, img, dv, ds = bufs[i]
+            topo = h.topology(c.F, n_verts=len(c.V))
+            V = torch.tensor(c.V, device="cuda:0")
+            if i in otfs:
+                a_img, a_dv, _ = dm.batch_run(h, [(V, topo, None, g, G, otfs[i])])[0]
+                eq = torch.equal(a_img, img) and torch.equal(a_dv, dv)
+            else:
+                a_img, a_dv, a_ds = dm.batch_run(h, [(V, topo, f32_sigma(c.sigma), g, G)])[0]
+                eq = torch.equal(a_img, img) and torch.equal(a_dv, dv) and torch.equal(a_ds, ds)
+            say(f"request {i} ({'otf' if i in otfs else 'gaussian'}): served equals alone: {eq}")
+            assert eq
+    finally:
+        srv.close()
