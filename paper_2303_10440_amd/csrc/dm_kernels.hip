@@ -654,13 +654,24 @@ struct FwdLds {
   float2 fb[4][FWD_J][64];
 };
 
-// Queue item: triangle tag, entry step j and lane.  The lane is made opaque
-// so that the item is built where it is stored, in the rarely taken append
-// branches; otherwise the compiler keeps one precomputed item per step in a
-// vector register through the whole main loop.
-__device__ __forceinline__ uint16_t queue_item(int tag, int j, int lane) {
+// Forward-sweep queue item: triangle tag, entry step j and lane.  The lane is
+// made opaque so that the item is built where it is stored, in the rarely
+// taken append branches; otherwise the compiler keeps one precomputed item per
+// step in a vector register through the whole main loop.
+__device__ __forceinline__ uint16_t fwd_queue_item(int tag, int j, int lane) {
   asm volatile("" : "+v"(lane));
   return (uint16_t)((tag << 9) | (j << 6) | lane);
+}
+// Gradient-sweep queue item, the same fields.  The step is added by an
+// opaque instruction, so that the item is built where it is stored, in the
+// append branches; otherwise the compiler keeps one precomputed item per
+// step in a vector register through the whole main loop.
+__device__ __forceinline__ uint16_t queue_item(int tag, int j, int lane) {
+  const int x = (tag << 9) | lane;
+  if (j == 0) return (uint16_t)x;
+  int y;
+  asm volatile("v_or_b32 %0, %1, %2" : "=v"(y) : "n"(j << 6), "v"(x));
+  return (uint16_t)y;
 }
 // The same item with the lane left visible to the compiler: the batched
 // surface-density gradient sweep spills inside its triangle loop with the
@@ -723,7 +734,7 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
       if ((MODE == 0 ? small : !fast) && valid) {
         const int pos = nq[0] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bs >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bs, 0u));
-        queue[0][pos] = queue_item(tag, j, lane);
+        queue[0][pos] = fwd_queue_item(tag, j, lane);
       }
       nq[0] += __popcll(bs);
     }
@@ -731,7 +742,7 @@ __device__ __forceinline__ void fwd_lanes_tri(const float* r, bool start, int ta
       if (close && !small && valid) {
         const int pos = nq[1] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bc >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bc, 0u));
-        queue[1][pos] = queue_item(tag, j, lane);
+        queue[1][pos] = fwd_queue_item(tag, j, lane);
       }
       nq[1] += __popcll(bc);
     }
@@ -1088,42 +1099,55 @@ struct VjpRing {
 // Closed-form gradient pair from the phase factors of the three nodes with
 // the adjoint weight's phase folded in (G_p = e^{-2 pi i (t_p - phi_W)}) and
 // the relative phases a, b in radians (2 pi times the a, b above).  With use false
-// every output is exactly zero (the common factor 1 / (2 pi a b c) is
-// replaced by zero, so a vanishing gap cannot produce inf or NaN).  With AMP
+// every output is exactly zero (the common factor 1 / (a b c) is replaced by
+// zero, so a vanishing gap cannot produce inf or NaN).  With AMP
 // the weight's modulus is folded into the Lagrange coefficients; without it
 // the outputs are those of a unit modulus (the caller scales them) and
 //   wf + i Pi = sum_p k_p G_p = e^{2 pi i phi_W} f_T,
 // the forward value of the pair in the weight's phase frame.
+//
+// The Lagrange coefficients k0 = -1/(ab), k1 = 1/(ac), k2 = -1/(bc) are
+// -c, b, -a times 1/(abc), and the node reciprocals follow from them:
+// 1/a = c k1, 1/b = -a k0, 1/c = a k1.  Grouping the repeated-node terms by
+// node pair, DD4_0 = T0 + i[(1/a)(T0 + T1) + (1/b)(T0 + T2)] and likewise for
+// the other two nodes, so the three share the three pair sums.
 template <int MODE, bool AMP>
 __device__ __forceinline__ void lag_pair_g(float a, float b, bool use, float amp, float G0r, float G0i, float G1r,
                                            float G1i, float G2r, float G2i, float& wf, float z[3], float& Pi) {
   const float c = b - a;
-  const float ab = a * b;
-  const float rD = use ? __builtin_amdgcn_rcpf(ab * c) : 0.0f;   // 1 / (a b c), radians
-  const float al = b * c * rD, be = a * c * rD, ga = ab * rD;
-  float k0, k1, k2;
+  const float rD = use ? __builtin_amdgcn_rcpf(a * b * c) : 0.0f;   // 1 / (a b c), radians
+  float k0, k1, k2, al, be, ga;
   if (AMP) {
-    const float alw = amp * al;
-    k0 = -alw * be;
-    k1 = alw * ga;
-    k2 = -amp * (be * ga);
+    const float rw = amp * rD, k1u = b * rD;
+    k0 = -c * rw;
+    k1 = b * rw;
+    k2 = -a * rw;
+    al = c * k1u;
+    ga = a * k1u;
+    be = a * (c * rD);
   } else {
-    k0 = -(al * be);
-    k1 = al * ga;
-    k2 = -(be * ga);
+    k0 = -c * rD;
+    k1 = b * rD;
+    k2 = -a * rD;
+    al = c * k1;
+    be = -a * k0;
+    ga = a * k1;
   }
   const float R0 = k0 * G0r, I0 = k0 * G0i, R1 = k1 * G1r, I1 = k1 * G1i, R2 = k2 * G2r, I2 = k2 * G2i;
-  const float s01 = al + be, s21 = ga - al, s12 = be + ga;
-  wf = R0 + R1 + R2;
-  Pi = I0 + I1 + I2;
   if (MODE == 0) {
-    z[0] = fmaf(-s01, I0, fmaf(-al, I1, fmaf(-be, I2, R0)));
-    z[1] = fmaf(-s21, I1, fmaf(al, I0, fmaf(-ga, I2, R1)));
-    z[2] = fmaf(s12, I2, fmaf(be, I0, fmaf(ga, I1, R2)));
+    const float u01 = I0 + I1, u02 = I0 + I2, u12 = I1 + I2;
+    z[0] = fmaf(-be, u02, fmaf(-al, u01, R0));
+    z[1] = fmaf(-ga, u12, fmaf(al, u01, R1));
+    z[2] = fmaf(ga, u12, fmaf(be, u02, R2));
+    wf = R0 + R1 + R2;
+    Pi = I0 + u12;
   } else {
-    z[0] = fmaf(s01, R0, fmaf(al, R1, fmaf(be, R2, I0)));
-    z[1] = fmaf(s21, R1, fmaf(-al, R0, fmaf(ga, R2, I1)));
-    z[2] = fmaf(-s12, R2, fmaf(-be, R0, fmaf(-ga, R1, I2)));
+    const float v01 = R0 + R1, v02 = R0 + R2, v12 = R1 + R2;
+    z[0] = fmaf(be, v02, fmaf(al, v01, I0));
+    z[1] = fmaf(ga, v12, fmaf(-al, v01, I1));
+    z[2] = fmaf(-ga, v12, fmaf(-be, v02, I2));
+    wf = R0 + v12;
+    Pi = I0 + I1 + I2;
   }
 }
 
