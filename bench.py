@@ -12,6 +12,11 @@ value = triangles x band entries / step time (each frequency-triangle pair is
 evaluated once forward and once for the gradient per step; with dL/dI given
 and the image wanted, dm_render_vjp does both in one fused sweep).
 
+Besides the headline step the default run measures the 64-cell batch against
+64 single calls (--no-batch skips it) and a short serving comparison of the
+batched server against one call per mesh at a saturating arrival rate
+(--no-serve-quick skips it); profiler runs of the headline kernels pass both.
+
 Prints ONE JSON line.  Synthetic data (seeded); no dataset.
 """
 from __future__ import annotations
@@ -419,10 +424,12 @@ def bench_smooth(dm, reps: int = 20) -> dict:
 
 
 def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_inflight: int, pool: int = 32,
-                seed: int = 0) -> dict:
+                seed: int = 0, abba: bool = False) -> dict:
     """cfg5: Poisson arrivals of forward + gradient requests on resident cells
     (n_t log-uniform [500, 40k], grids {64^3, 128^3, 256x256x128}); latency is
-    submission to completion as seen by the server."""
+    submission to completion as seen by the server.  With abba the trace is
+    replayed batched, plain, plain, batched and each mode reports the mean of
+    its two replays (slow drifts of the device's clocks cancel)."""
     import torch
     from workloads import configs
     cases, t_arr, idx, widx = configs.cfg5_pooled(seed, count, rate, pool, warmup)
@@ -472,10 +479,21 @@ def bench_serve(dm, rate: float, count: int, warmup: int, max_batch: int, max_in
                        "(n_t log-uniform [500, 40k], grids {64^3, 128^3, 256x256x128}, own PSF per cell), "
                        "forward + gradient each",
            "rate": rate, "offered_pairs_per_s": rate * float(np.mean([pairs_of[int(i)] for i in idx]))}
-    out["batched"] = run(max_batch, max_inflight)
-    print(f"serve {rate:g}/s batched: {out['batched']}", file=sys.stderr, flush=True)
-    out["plain"] = run(1, 1)
-    print(f"serve {rate:g}/s plain: {out['plain']}", file=sys.stderr, flush=True)
+    order = ("batched", "plain", "plain", "batched") if abba else ("batched", "plain")
+    runs = {"batched": [], "plain": []}
+    for mode in order:
+        r = run(max_batch, max_inflight) if mode == "batched" else run(1, 1)
+        runs[mode].append(r)
+        print(f"serve {rate:g}/s {mode}: {r}", file=sys.stderr, flush=True)
+    for mode, rs in runs.items():
+        if len(rs) == 1:
+            out[mode] = rs[0]
+        else:
+            m = {k: float(np.mean([r[k] for r in rs])) for k in ("p50_ms", "p99_ms", "mean_ms", "throughput_rps",
+                                                                  "pairs_per_s", "mean_batch")}
+            m["ok"] = all(r["ok"] for r in rs)
+            m["replays"] = rs
+            out[mode] = m
     out["throughput_gain"] = out["batched"]["throughput_rps"] / out["plain"]["throughput_rps"]
     return out
 
@@ -488,7 +506,11 @@ def main() -> int:
     ap.add_argument("--mode", choices=["volume", "surface"], default="volume")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", action="store_true", help="add the 64-cell batched vs looped comparison")
+    ap.add_argument("--batch", action=argparse.BooleanOptionalAction, default=True,
+                    help="the 64-cell batched vs looped comparison (on by default)")
+    ap.add_argument("--serve-quick", action=argparse.BooleanOptionalAction, default=True,
+                    help="a short serving comparison at a saturating rate: 300 requests at 100/s "
+                         "(on by default; --serve gives the full per-rate sweep)")
     ap.add_argument("--sweeps", action="store_true",
                     help="add the paper's mesh-transform benchmark shapes (image size, triangle count)")
     ap.add_argument("--otf", action="store_true",
@@ -503,6 +525,8 @@ def main() -> int:
                     help="add the serving comparison at these arrival rates (req/s)")
     ap.add_argument("--serve-count", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-abba", action="store_true",
+                    help="replay each serving trace batched, plain, plain, batched and report per-mode means")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -649,8 +673,10 @@ def main() -> int:
         out["foam"] = bench_foam(dm)
     if args.otf:
         out["otf"] = bench_otf(dm, case)
+    if args.serve_quick:
+        out["serving_quick"] = bench_serve(dm, 100.0, 300, 30, 16, 2)
     if args.serve is not None:
-        out["serving"] = [bench_serve(dm, r, args.serve_count, args.serve_warmup, 16, 2)
+        out["serving"] = [bench_serve(dm, r, args.serve_count, args.serve_warmup, 16, 2, abba=args.serve_abba)
                           for r in (args.serve or [200.0])]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, g, sigma, mode, args.cpu_seconds)
