@@ -248,3 +248,50 @@ def test_served_tabulated_otf_requests(dm):
             assert eq
     finally:
         srv.close()
+
+
+def test_large_request_runs_alone_unless_a_backlog_builds(dm):
+    """The scheduling rule for large requests (their own sweep launches, here
+    the single cell, 2.8e9 pairs): with fewer than max_batch requests waiting,
+    small requests submitted while it runs start only after it completes;
+    once max_batch of them wait they start beside it.  Launch and completion
+    times come from the server's per-request results (queue_ms, total_ms)
+    and the submission times measured here."""
+    import torch
+    say("serve: large request alone unless backlog")
+    big = configs.cfg3(VOLUME)
+    small = _cells(3, seed=13)
+
+    def run(max_batch):
+        srv = dm.Server(0, max_batch=max_batch, max_inflight=2)
+        try:
+            mb = srv.mesh_add(big.V, big.F)
+            ms = [srv.mesh_add(c.V, c.F) for c in small]
+            bb = _buffers(big, 70)
+            bs = [_buffers(c, 71 + i) for i, c in enumerate(small)]
+            # warm-up: bands, FFT plans and workspace of every request
+            ts = [srv.submit(mb, f32_sigma(big.sigma), *bb)]
+            ts += [srv.submit(m, f32_sigma(c.sigma), *b) for m, c, b in zip(ms, small, bs)]
+            assert all(srv.poll(t)["status"] == 0 for t in ts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tl = srv.submit(mb, f32_sigma(big.sigma), *bb)
+            subs = []
+            for m, c, b in zip(ms, small, bs):
+                subs.append((time.perf_counter() - t0, srv.submit(m, f32_sigma(c.sigma), *b)))
+            rl = srv.poll(tl)
+            rs = [(dt, srv.poll(t)) for dt, t in subs]
+            assert rl["status"] == 0 and all(r["status"] == 0 for _, r in rs)
+            done_l = rl["total_ms"]   # from the large request's submission (t0)
+            starts = [1e3 * dt + r["queue_ms"] for dt, r in rs]
+            say(f"  max_batch {max_batch}: large done at {done_l:.2f} ms, small starts "
+                + ", ".join(f"{x:.2f}" for x in starts))
+            return done_l, starts
+        finally:
+            srv.close()
+
+    done_l, starts = run(16)
+    assert done_l > 1.0
+    assert all(x >= done_l - 0.3 for x in starts)
+    done_l, starts = run(2)
+    assert min(starts) < done_l - 0.5
