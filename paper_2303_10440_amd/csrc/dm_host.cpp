@@ -90,9 +90,14 @@ constexpr size_t BAND_CACHE_MAX_BYTES = (size_t)4 << 30;
 // events that fork work onto it and join it back.  A handle has one for
 // dm_batch_run; each serving slot has its own, so batches in flight on
 // different slots do not queue behind each other's second stream.
+// Streams beside a call's own stream (default priority, non-blocking): the
+// small per-request steps of a batch are spread over them, and large requests
+// alternate with the call's stream.  fork orders them after the call's stream,
+// join[k] orders the call's stream after stream k.
+constexpr int AUX_STREAMS = 3;
 struct AuxStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t s[AUX_STREAMS] = {};
+  hipEvent_t fork = nullptr, join[AUX_STREAMS] = {};
 };
 
 struct BandKey {
@@ -603,16 +608,37 @@ dm_status begin_call(dm_handle* h, hipStream_t s) {
 }
 
 dm_status ensure_aux(AuxStream* a) {
-  if (!a->s) HIP_TRY(hipStreamCreateWithFlags(&a->s, hipStreamNonBlocking));
   if (!a->fork) HIP_TRY(hipEventCreateWithFlags(&a->fork, hipEventDisableTiming));
-  if (!a->join) HIP_TRY(hipEventCreateWithFlags(&a->join, hipEventDisableTiming));
+  for (int k = 0; k < AUX_STREAMS; ++k) {
+    if (!a->s[k]) HIP_TRY(hipStreamCreateWithFlags(&a->s[k], hipStreamNonBlocking));
+    if (!a->join[k]) HIP_TRY(hipEventCreateWithFlags(&a->join[k], hipEventDisableTiming));
+  }
+  return DM_OK;
+}
+
+// Orders the first n aux streams after everything enqueued so far on s.
+dm_status aux_fork(AuxStream* a, int n, hipStream_t s) {
+  if (n <= 0) return DM_OK;
+  HIP_TRY(hipEventRecord(a->fork, s));
+  for (int k = 0; k < n; ++k) HIP_TRY(hipStreamWaitEvent(a->s[k], a->fork, 0));
+  return DM_OK;
+}
+
+// Orders s after everything enqueued so far on the first n aux streams.
+dm_status aux_join(AuxStream* a, int n, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    HIP_TRY(hipEventRecord(a->join[k], a->s[k]));
+    HIP_TRY(hipStreamWaitEvent(s, a->join[k], 0));
+  }
   return DM_OK;
 }
 
 void destroy_aux(AuxStream* a) {
   if (a->fork) (void)hipEventDestroy(a->fork);
-  if (a->join) (void)hipEventDestroy(a->join);
-  if (a->s) (void)hipStreamDestroy(a->s);
+  for (int k = 0; k < AUX_STREAMS; ++k) {
+    if (a->join[k]) (void)hipEventDestroy(a->join[k]);
+    if (a->s[k]) (void)hipStreamDestroy(a->s[k]);
+  }
   *a = AuxStream{};
 }
 
@@ -1071,9 +1097,10 @@ void layout_batch(std::vector<ReqPlan>& P, BatchLayout& L) {
 // The part of a batch after the pre-steps: the shared persistent launch and
 // its requests' post-steps on s, then the large requests, alternating between
 // s and s2 (the same stream when there is no second one).
-template <typename Done>
+template <typename Done, typename Fork, typename Join>
 dm_status enqueue_batch_rest(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, char* base, hipStream_t s,
-                             hipStream_t s2, Done& done) {
+                             hipStream_t s2, Done& done, const std::vector<hipStream_t>& lanes, Fork& lanes_fork,
+                             Join& lanes_join) {
   const size_t n = P.size();
   if (!L.items.empty() || L.fused_tiles[0] > 0 || L.fused_tiles[1] > 0) {
     if (!L.items.empty())
@@ -1095,11 +1122,16 @@ dm_status enqueue_batch_rest(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout&
                                reinterpret_cast<int*>(base + L.o_counter), s));
     tm.done();
   }
+  DM_TRY(lanes_fork());
+  // the post-steps of the shared launch's requests, spread over the lanes
+  int j = 0;
   for (size_t i = 0; i < n; ++i)
     if (!P[i].direct) {
-      DM_TRY(stage_post(h, P[i], s));
-      DM_TRY(done(i, s));
+      const hipStream_t st = lanes[(size_t)(j++) % lanes.size()];
+      DM_TRY(stage_post(h, P[i], st));
+      DM_TRY(done(i, st));
     }
+  DM_TRY(lanes_join());
   int k = 0;
   for (size_t i = 0; i < n; ++i)
     if (P[i].direct) {
@@ -1144,21 +1176,43 @@ dm_status enqueue_batch(dm_handle* h, std::vector<ReqPlan>& P, BatchLayout& L, c
     if (req_done && (*req_done)[i]) HIP_TRY(hipEventRecord((*req_done)[i], st));
     return DM_OK;
   };
-  for (size_t i = 0; i < n; ++i) DM_TRY(stage_pre(h, P[i], s));
+  // The requests' small steps (pre-steps before the shared launch, post-steps
+  // after it) do not fill the GPU one request at a time: they are dealt over
+  // up to 1 + AUX_STREAMS lanes (s and aux streams forked from it, joined back
+  // into s before the shared launch and after the post-steps).  Every request
+  // works in its own region of the batch memory with its own FFT buffers, so
+  // requests on different lanes share nothing but read-only inputs.
+  const int n_aux = (int)std::min<size_t>(AUX_STREAMS, n > 0 ? n - 1 : 0);
+  if (n_aux > 0 || n_direct >= 2) DM_TRY(ensure_aux(aux));
+  std::vector<hipStream_t> lanes{s};
+  for (int k = 0; k < n_aux; ++k) lanes.push_back(aux->s[k]);
+  bool forked = false;
+  auto lanes_fork = [&]() -> dm_status {
+    DM_TRY(aux_fork(aux, n_aux, s));
+    forked = n_aux > 0;
+    return DM_OK;
+  };
+  auto lanes_join = [&]() -> dm_status {
+    if (!forked) return DM_OK;
+    forked = false;
+    return aux_join(aux, n_aux, s);
+  };
+  dm_status st = lanes_fork();
+  for (size_t i = 0; i < n && st == DM_OK; ++i) st = stage_pre(h, P[i], lanes[i % lanes.size()]);
+  // join even after a failed enqueue, so that s never runs ahead of an aux stream
+  const dm_status jst = lanes_join();
+  if (st != DM_OK) return st;
+  DM_TRY(jst);
   hipStream_t s2 = s;
   if (n_direct >= 2) {
-    DM_TRY(ensure_aux(aux));
-    HIP_TRY(hipEventRecord(aux->fork, s));
-    HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
-    s2 = aux->s;
+    DM_TRY(aux_fork(aux, 1, s));
+    s2 = aux->s[0];
   }
-  const dm_status st = enqueue_batch_rest(h, P, L, base, s, s2, done);
-  if (s2 != s) {
-    // join even after a failed enqueue, so that s never runs ahead of s2
-    HIP_TRY(hipEventRecord(aux->join, s2));
-    HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
-  }
-  return st;
+  st = enqueue_batch_rest(h, P, L, base, s, s2, done, lanes, lanes_fork, lanes_join);
+  const dm_status jst2 = lanes_join();
+  if (s2 != s) DM_TRY(aux_join(aux, 1, s));
+  if (st != DM_OK) return st;
+  return jst2;
 }
 
 }  // namespace
