@@ -674,9 +674,10 @@ __device__ __forceinline__ uint16_t queue_item(int tag, int j, int lane) {
   return (uint16_t)y;
 }
 // The same item with the lane left visible to the compiler: the batched
-// surface-density gradient sweep spills inside its triangle loop with the
-// opaque form and not with this one (measured on the compiler's resource
-// report), so that kernel alone uses it.
+// surface-density sweeps (gradient and fused) spill inside their triangle
+// loops with the opaque form (the fused one 34 registers, 22 reloads per
+// triangle, a third slower) and much less with this one, so those kernels use
+// it.
 __device__ __forceinline__ uint16_t plain_item(int tag, int j, int lane) {
   return (uint16_t)((tag << 9) | (j << 6) | lane);
 }
@@ -1670,7 +1671,8 @@ __global__ void __launch_bounds__(SWEEP_T, MODE == 0 ? FUSED_WAVES_VOLUME : FUSE
     const int local = tile - q.tile0;
     const int c = local / q.ntr, y = local - c * q.ntr;
     const int t0 = y * q.vtpb, t1 = min(q.nt, t0 + q.vtpb);
-    vjp_lanes_tile<MODE, J, true>(q.rec, q.nt, t0, t1, q.erec, q.nE, (int64_t)c * fused_chunk(MODE), 1, q.tpx, q.tpy,
+    vjp_lanes_tile<MODE, J, true, MODE == 0>(q.rec, q.nt, t0, t1, q.erec, q.nE, (int64_t)c * fused_chunk(MODE), 1,
+                                             q.tpx, q.tpy,
                                   q.tpz, q.vpart + (size_t)c * NC * q.nt, q.fpart + (size_t)y * q.nE, L);
   }
 }
