@@ -51,6 +51,11 @@ constexpr float INV_TWO_PI_F = 0.15915494309189535f;
 // relative phases in radians.
 constexpr float LAG_GAP_RAD = 0.06283185307179587f;   // 0.01 rev
 constexpr float SERIES_RAD = 1.0f;
+// Below one radian of spread the closed form is still used when the smallest
+// gap times the spread is at least LAG_GAP_SPREAD: its float32 error grows like
+// 1 / (smallest gap x spread), so those pairs are no less accurate than pairs
+// at the gap threshold with a spread of one radian or more.
+constexpr float LAG_GAP_SPREAD = LAG_GAP_RAD * SERIES_RAD;
 
 // e^{-2 pi i r} for r in revolutions, r already in [-1/2, 1/2].
 __device__ __forceinline__ void cis_neg(float r, float& c, float& s_neg) {
@@ -1218,7 +1223,7 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
     const float c = b - a;
     const float mn = fminf(fminf(fabsf(a), fabsf(b)), fabsf(c));
     const float mx = fmaxf(fmaxf(fabsf(a), fabsf(b)), fabsf(c));
-    const bool close = mn < LAG_GAP_RAD, small = mx < SERIES_RAD;
+    const bool close = mn < LAG_GAP_RAD, small = mx < SERIES_RAD && mn * mx < LAG_GAP_SPREAD;
     const bool fast = !close && !small;
     float wf = 0.0f, z[3], Pi;
     lag_pair_g<MODE, AMP>(a, b, fast, amp[j], Xr[j], Xi[j], Yr[j], Yi[j], Nr, Ni, wf, z, Pi);
