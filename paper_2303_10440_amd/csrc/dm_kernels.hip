@@ -443,6 +443,12 @@ __global__ void k_band_fill_otf(GridC g, const float2* __restrict__ otf, double 
     return;
   }
   const int e0 = off[slot];
+  // the band's arrays hold b.n_entries entries (the count the caller planned
+  // with); a table changed since that count must not write past them
+  if ((int64_t)e0 + c > b.n_entries) {
+    b.map[p] = -1;
+    return;
+  }
   b.map[p] = e0 | ((c - 1) << 30);
   const Aliases a = aliases_of(g, ix, iy, iz);
   for (int j = 0; j < a.n; ++j) {
