@@ -46,7 +46,7 @@ def _problem(mode):
 
 @pytest.mark.parametrize("mode", [configs.VOLUME, configs.SURFACE])
 def test_fit_gradients_equal_oracle(dm, handle, ref, mode):
-    """The driver's shape step (weighted L2, narrow band) and PSF step (plain
+    """The fitting driver's shape step (weighted L2, narrow band) and PSF step (plain
     L2, full spectrum): losses and gradients against the same quantities
     built from the oracle's image and gradients."""
     from paper_2303_10440_amd import fit
