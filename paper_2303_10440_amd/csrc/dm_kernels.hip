@@ -1259,10 +1259,13 @@ __device__ __forceinline__ void vjp_lanes_main(const float* r, bool start, int t
       Fr[j] = fmaf(wt, wf, Fr[j]);
       Fi[j] = fmaf(wt, Pi, Fi[j]);
     }
-    // Ballots of plain compares are the compares' own lane masks.  Lanes past
-    // the end of the band (all phases 0) are queued too and skipped by the
-    // passes.
-    const uint64_t bs = __builtin_amdgcn_ballot_w64(small);
+    // Ballots of plain compares are the compares' own lane masks; the ballot
+    // of the combined condition small would be rebuilt from a vector register
+    // (two more instructions per pair), so its mask is the AND of its two
+    // compares' ballots.  Lanes past the end of the band (all phases 0) are
+    // queued too and skipped by the passes.
+    const uint64_t bs =
+        __builtin_amdgcn_ballot_w64(mx < SERIES_RAD) & __builtin_amdgcn_ballot_w64(mn * mx < LAG_GAP_SPREAD);
     const uint64_t bc = __builtin_amdgcn_ballot_w64(close) & ~bs;
     if (bs) {
       if (small) {
