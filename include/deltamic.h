@@ -84,8 +84,13 @@ typedef enum {
 typedef struct dm_handle dm_handle;
 typedef struct dm_topology dm_topology;
 
+/* Most voxels along one grid axis: the sweeps pass vertex phases of up to
+ * (sum of |k_j|) / 8192 + 1 revolutions to the hardware sine and cosine,
+ * whose domain is [-256, 256] revolutions. */
+#define DM_MAX_AXIS (1 << 20)
+
 typedef struct {
-  int32_t n[3];         /* voxels along x, y, z (each >= 1) */
+  int32_t n[3];         /* voxels along x, y, z (each in [1, DM_MAX_AXIS]) */
   float spacing[3];     /* voxel size along x, y, z (> 0) */
   float origin[3];      /* position of voxel (0,0,0) */
   float band_tau;       /* band threshold on the PSF transform, in [0, inf) */

@@ -94,13 +94,18 @@ __device__ __forceinline__ float vertex3_phase(float kx, float ky, float kz, con
   th -= __builtin_rintf(th);
   return th + fmaf(kz, r[5], fmaf(ky, r[4], kx * r[3]));
 }
-// frac(w - k.u3) in [0, 1): the fraction of the exact grid part (v_fract is
-// exact there), then the rest, with w (a phase in revolutions, e.g. the
-// adjoint weight's) folded into it.
+// w - k.u3 up to an integer (revolutions): the fraction of the exact grid
+// part (v_fract is exact there), then the rest, with w (a phase in
+// revolutions, e.g. the adjoint weight's, at most 1/2 in magnitude) folded
+// into it.  The rest is at most sum |k_j| / 8192 + 1/2 in magnitude, so with
+// at most 2^20 samples per grid axis the result lies within (-194, 194): the
+// hardware sine and cosine take it as it is (their domain is [-256, 256]
+// revolutions, and on the device they agree with the argument wrapped into
+// [0, 1), more closely near zero, where the wrap loses the low bits).
 __device__ __forceinline__ float vertex3_wphase(float kx, float ky, float kz, const float* r, float w) {
   const float th = fmaf(kz, r[2], fmaf(ky, r[1], kx * r[0]));   // exact: 12-bit grid part
   const float lo = fmaf(kz, r[5], fmaf(ky, r[4], fmaf(kx, r[3], -w)));
-  return __builtin_amdgcn_fractf(__builtin_amdgcn_fractf(-th) - lo);
+  return __builtin_amdgcn_fractf(-th) - lo;
 }
 // Phases of vertices 2 and 3 relative to vertex 1 in radians (the record
 // holds the edges times 2 pi / L).

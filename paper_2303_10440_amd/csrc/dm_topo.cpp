@@ -30,6 +30,9 @@ Check validate_grid(const dm_grid* g) {
   if (!g) return bad(DM_ERR_ARG, "grid is NULL");
   for (int j = 0; j < 3; ++j) {
     if (g->n[j] < 1) return bad(DM_ERR_ARG, "grid n[%d] = %d must be >= 1", j, g->n[j]);
+    // keeps every vertex phase the sweeps pass to the hardware sine and
+    // cosine inside their domain of [-256, 256] revolutions
+    if (g->n[j] > DM_MAX_AXIS) return bad(DM_ERR_ARG, "grid n[%d] = %d exceeds %d", j, g->n[j], DM_MAX_AXIS);
     if (!(g->spacing[j] > 0.0f) || !std::isfinite(g->spacing[j]))
       return bad(DM_ERR_ARG, "grid spacing[%d] must be finite and > 0", j);
     if (!std::isfinite(g->origin[j])) return bad(DM_ERR_ARG, "grid origin[%d] must be finite", j);

@@ -325,6 +325,14 @@ static void test_grid_and_psf() {
     b = good_grid();
     b.n[0] = b.n[1] = b.n[2] = 1 << 30;   // far beyond the position limit (no overflow)
     EXPECT(dm::validate_grid(&b).st == DM_ERR_ARG);
+    for (int j = 0; j < 3; ++j) {   // the per-axis limit, on grids of few positions
+      b = good_grid();
+      b.n[0] = b.n[1] = b.n[2] = 1;
+      b.n[j] = DM_MAX_AXIS;
+      EXPECT(dm::validate_grid(&b).st == DM_OK);
+      b.n[j] = DM_MAX_AXIS + 1;
+      EXPECT(dm::validate_grid(&b).st == DM_ERR_ARG);
+    }
   }
   dm_psf p{};
   EXPECT(dm::validate_psf(nullptr).st == DM_ERR_ARG);
