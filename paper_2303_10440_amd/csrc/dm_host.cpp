@@ -552,13 +552,22 @@ SweepPlan plan_fused(int64_t nE, int nt, int mode) {
 // The fused plan of a request inside a batch's shared launch: the same entry
 // chunks, triangle ranges of at least FUSED_BATCH_TILE_PAIRS / fused_chunk
 // triangles (the whole mesh when it is smaller), so that many small requests
-// do not turn into many small tiles; the shared queue fills the GPU.
+// do not turn into many small tiles; the shared queue fills the GPU.  But a
+// request is cut into at least FUSED_BATCH_MIN_TILES tiles (four rounds of
+// resident workgroups) where ranges of the single-call plan's size allow it:
+// a small request that runs alone (a server at low load) still spreads over
+// the GPU instead of a few dozen workgroups, and the shared queue's tail is
+// shorter.  The plan depends on the request alone.
 constexpr int64_t FUSED_BATCH_TILE_PAIRS = (int64_t)1 << 22;
+constexpr int64_t FUSED_BATCH_MIN_TILES = 4096;
 
 SweepPlan plan_fused_batch(int64_t nE, int nt, int mode) {
   SweepPlan sp = plan_fused(nE, nt, mode);
+  const int64_t n = std::max(nt, 1);
   const int64_t want = (FUSED_BATCH_TILE_PAIRS + fused_chunk(mode) - 1) / fused_chunk(mode);
-  sp.tpb = (int)std::max<int64_t>(sp.tpb, std::min<int64_t>(std::max(nt, 1), want));
+  const int64_t ranges = std::max<int64_t>(1, (FUSED_BATCH_MIN_TILES + sp.n_chunks - 1) / sp.n_chunks);
+  const int64_t cap = (n + ranges - 1) / ranges;   // triangles per range for that many ranges
+  sp.tpb = (int)std::max<int64_t>(sp.tpb, std::min(n, std::min(want, cap)));
   return sp;
 }
 
