@@ -318,7 +318,9 @@ dm_status dm_render_otf_vjp(dm_handle* h, const dm_mesh* mesh, const void* otf, 
  * FFTs, adjoint weights, reductions) run around them on the same stream.  A
  * request with dL_dimage and both an image (or dL_dsigma) and dL_dverts runs
  * dm_render_vjp's fused sweep in tiles of at least 4M (entry, triangle)
- * pairs; forward-only and gradient-only requests have tiles of their own.
+ * pairs, but in no fewer than 4096 tiles where triangle ranges of the single
+ * call's size allow it (so a small request alone still spreads over the GPU);
+ * forward-only and gradient-only requests have tiles of their own.
  * Results equal the single calls' up to float32 summation order.  Each
  * request's tiles and summation order depend on that request alone, so its
  * results are bitwise the same whatever else is in the batch.  A request with
