@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dm_plan.h"   // sweep sizes (entries per lane and per block), launch planning
 #include "dm_topo.h"   // strip flags, neighbour-table width
 
 namespace dm {
@@ -52,23 +53,6 @@ constexpr float PHASE_GRID = 4096.0f;   // 2^12
 // Band-entry record of the VJP sweeps: ERC float4 per entry,
 //  {kx, ky, kz, Wr}, {Wi, xi_x, xi_y, xi_z}, {|W|, arg(W) / (2 pi), 0, 0}
 constexpr int ERC = 3;
-
-// Lane-per-entry gradient sweep: vjp_j(mode) band entries per lane (entry
-// chunks of 4 waves x 64 lanes x vjp_j(mode) entries), chosen with the
-// occupancy: 5 per lane at 5 waves per SIMD (volume), 6 at 4 waves (surface,
-// whose ten accumulators per triangle need the larger register budget).
-constexpr int VJP_J_MAX = 8;
-constexpr int vjp_j(int mode) { return mode == 0 ? 5 : 6; }
-constexpr int vjp_chunk(int mode) { return 256 * vjp_j(mode); }
-// Fused forward and gradient sweep (given cotangent): one entry per lane fewer
-// than the gradient sweep, for the forward sums each entry carries; blocks of
-// one chunk of fused_chunk(mode) entries.
-constexpr int fused_j(int mode) { return mode == 0 ? 4 : 4; }
-constexpr int fused_chunk(int mode) { return 256 * fused_j(mode); }
-// Forward sweep: FWD_J band entries per lane, FWD_CHUNK entries per block.
-constexpr int FWD_J = 3;
-constexpr int FWD_CHUNK = 256 * FWD_J;
-static_assert(FWD_J <= 8 && VJP_J_MAX <= 8, "queued pairs store the entry step in 3 bits");
 
 // Work item of the persistent batched sweeps: one tile of one request's
 // forward sweep (kind 0: FWD_CHUNK band entries from x0, triangle chunk c) or
@@ -147,7 +131,6 @@ hipError_t launch_dsig_final(const double* dsig_part, int nblk, float* out6, hip
 // Lane-per-entry gradient sweep: n_chunks blocks along the band, each covering
 // chunks_per_block x vjp_chunk(mode) entries, times triangle chunks of tris_per_block
 // (at most VJP_TPB_MAX); same partial layout [chunk][NC][nt].
-constexpr int VJP_TPB_MAX = 256;
 hipError_t launch_vjp_lanes(int mode, const GridC& g, const float* tri_rec, int nt, int tris_per_block,
                             int chunks_per_block, int n_chunks, const float4* erec, int64_t nE, float* part,
                             hipStream_t s);

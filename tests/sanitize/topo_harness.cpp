@@ -1,9 +1,12 @@
 // Host sanitizer harness of the renderer's host-side checks and mesh tables
-// (paper_2303_10440_amd/csrc/dm_topo.cpp), built alone with
-// -fsanitize=address,undefined by tests/test_sanitize_cpu.py.  Exercises
-// closed, open, non-manifold, degenerate, random and out-of-range face sets,
-// empty meshes, density weights and bad grids and covariances, and checks the
-// invariants of every table.  Exit status 0 iff every check holds.
+// (paper_2303_10440_amd/csrc/dm_topo.cpp) and of its sweep launch planning
+// (dm_plan.h), built alone with -fsanitize=address,undefined by
+// tests/test_sanitize_cpu.py.  Exercises closed, open, non-manifold,
+// degenerate, random and out-of-range face sets, empty meshes, density
+// weights, bad grids and covariances, and the sweep plans over a range of band
+// and mesh sizes, and checks the invariants of every table and plan.  Exit
+// status 0 iff every check holds.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -14,6 +17,7 @@
 #include <utility>
 #include <vector>
 
+#include "dm_plan.h"
 #include "dm_topo.h"
 
 using dm::Check;
@@ -362,10 +366,66 @@ static void test_grid_and_psf() {
   }
 }
 
+// Sweep plans: every entry and triangle covered, no empty range, the bounds
+// the kernels and partial buffers assume, and the shared launch's fused plan
+// against the single call's (same entry chunks, never more triangle ranges, so
+// never larger forward partials; tiles of at most max(single tile, 4M pairs);
+// at least min(single-call tiles, half the tile floor) tiles).
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static void test_plans() {
+  const int64_t nEs[] = {0, 1, 767, 768, 769, 1023, 1024, 1025, 45000, 140000, 549888, 1100000, 8585088};
+  const int nts[] = {0, 1, 31, 32, 33, 500, 1000, 2880, 5120, 20480, 40500};
+  for (int mode = 0; mode < 2; ++mode)
+    for (int64_t nE : nEs)
+      for (int nt : nts) {
+        const int64_t n = std::max(nt, 1);
+        const dm::SweepPlan f = dm::plan_fwd(nE, nt);
+        EXPECT(f.n_chunks >= 1 && f.per_chunk >= 1);
+        EXPECT((int64_t)f.n_chunks * f.per_chunk >= nt && (int64_t)(f.n_chunks - 1) * f.per_chunk < n);
+        EXPECT(nt < 32 || f.per_chunk >= 32);
+        const dm::SweepPlan v = dm::plan_vjp(nE, nt, mode);
+        EXPECT(v.n_chunks >= 1 && v.n_chunks <= 256 && v.sub >= 1);
+        EXPECT(v.per_chunk == v.sub * dm::vjp_chunk(mode));
+        EXPECT((int64_t)v.n_chunks * v.per_chunk >= nE);
+        EXPECT(v.tpb >= 1 && v.tpb <= dm::VJP_TPB_MAX);
+        const dm::SweepPlan s1 = dm::plan_fused(nE, nt, mode);
+        EXPECT(s1.per_chunk == dm::fused_chunk(mode) && s1.n_chunks == std::max<int64_t>(1, cdiv(nE, s1.per_chunk)));
+        EXPECT(s1.tpb >= 1 && (nt < 32 || s1.tpb >= 32));
+        const dm::SweepPlan r1 = dm::fused_fwd_plan(s1, nt);
+        EXPECT(r1.per_chunk == s1.tpb && (int64_t)r1.n_chunks * r1.per_chunk >= nt);
+        EXPECT((int64_t)(r1.n_chunks - 1) * r1.per_chunk < n);
+        const dm::SweepPlan sb = dm::plan_fused_batch(nE, nt, mode);
+        const dm::SweepPlan rb = dm::fused_fwd_plan(sb, nt);
+        EXPECT(sb.n_chunks == s1.n_chunks && sb.per_chunk == s1.per_chunk);
+        EXPECT(sb.tpb >= s1.tpb && rb.n_chunks <= r1.n_chunks);
+        EXPECT((int64_t)rb.n_chunks * rb.per_chunk >= nt && (int64_t)(rb.n_chunks - 1) * rb.per_chunk < n);
+        const int64_t want = cdiv(dm::FUSED_BATCH_TILE_PAIRS, dm::fused_chunk(mode));
+        EXPECT(sb.tpb <= std::max<int64_t>(s1.tpb, std::min(n, want)));
+        const int64_t tiles_s = (int64_t)s1.n_chunks * r1.n_chunks, tiles_b = (int64_t)sb.n_chunks * rb.n_chunks;
+        EXPECT(tiles_b >= std::min(tiles_s, dm::FUSED_BATCH_MIN_TILES / 2));
+        const dm::SweepPlan fb = dm::plan_fwd_batch(nE, nt);
+        EXPECT(fb.per_chunk >= 1 && fb.n_chunks <= 8 && (nt == 0 || fb.n_chunks >= 1));   // no sweep runs for nt = 0
+        EXPECT((int64_t)fb.n_chunks * fb.per_chunk >= nt && (nt < 640 || fb.per_chunk >= 640));
+        const dm::SweepPlan vb = dm::plan_vjp_batch(nE, nt, mode);
+        EXPECT(vb.n_chunks == v.n_chunks && vb.per_chunk == v.per_chunk);
+        EXPECT(vb.tpb >= 1 && vb.tpb <= dm::VJP_TPB_MAX && vb.tpb <= n);
+      }
+  // a small cell of the serving pool (64^3 band, 2880 triangles) alone in the
+  // shared launch: the single call's tiling, thousands of tiles, not dozens
+  const dm::SweepPlan s1 = dm::plan_fused(45000, 2880, 0), sb = dm::plan_fused_batch(45000, 2880, 0);
+  EXPECT(sb.tpb == s1.tpb && (int64_t)sb.n_chunks * dm::fused_fwd_plan(sb, 2880).n_chunks >= 2048);
+  // the single cell's band (549,888 entries, 5120 triangles): larger tiles than
+  // the single call's, still at least the tile floor
+  const dm::SweepPlan c1 = dm::plan_fused(549888, 5120, 0), cb = dm::plan_fused_batch(549888, 5120, 0);
+  EXPECT(cb.tpb > c1.tpb && (int64_t)cb.n_chunks * dm::fused_fwd_plan(cb, 5120).n_chunks >= dm::FUSED_BATCH_MIN_TILES);
+}
+
 int main() {
   test_meshes();
   test_weights();
   test_grid_and_psf();
+  test_plans();
   if (g_fail) {
     std::fprintf(stderr, "%d checks failed\n", g_fail);
     return 1;

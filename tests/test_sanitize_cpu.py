@@ -1,7 +1,9 @@
 """Host sanitizer build: the renderer's host-side checks and mesh tables
 (paper_2303_10440_amd/csrc/dm_topo.cpp: grid and covariance validation, face
 validation, closure and orientation, triangle strips, vertex incidence and
-adjacency, density-weight closure) and the FP64 oracle's C routines, each
+adjacency, density-weight closure), its sweep launch planning
+(paper_2303_10440_amd/csrc/dm_plan.h: coverage, bounds, the shared launch's
+tile floor) and the FP64 oracle's C routines, each
 compiled alone with -fsanitize=address,undefined and run on its harness
 (tests/sanitize/), which checks table invariants and closed forms on
 closed, open, non-manifold, degenerate, random and out-of-range inputs.
