@@ -84,9 +84,10 @@ typedef enum {
 typedef struct dm_handle dm_handle;
 typedef struct dm_topology dm_topology;
 
-/* Most voxels along one grid axis: the sweeps pass vertex phases of up to
- * (sum of |k_j|) / 8192 + 1 revolutions to the hardware sine and cosine,
- * whose domain is [-256, 256] revolutions. */
+/* Most voxels along one grid axis: the sweeps pass vertex phases of less
+ * than (sum of |k_j|) / 8192 + 3/2 revolutions in magnitude (k the integer
+ * frequency, at most n_j / 2 per axis) to the hardware sine and cosine, whose
+ * domain is [-256, 256] revolutions. */
 #define DM_MAX_AXIS (1 << 20)
 
 typedef struct {
